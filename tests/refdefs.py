@@ -1,0 +1,84 @@
+"""Independent, definition-level checks used to pin the oracle.
+
+Nothing here shares code with ``oracle/`` (C) or with the GPU library.  Each
+function restates a mathematical fact about grayscale reconstruction by
+dilation in numpy/scipy:
+
+* :func:`brute_numpy` -- the definition: J <- dilate(J) ^ I until stable
+  (the paper's reconstruction Equation and its iterative algorithm).
+* :func:`threshold_decomposition` -- the level-set characterisation: R(p) is
+  the largest level t such that p lies in a connected component of {I >= t}
+  that meets {J >= t}.  Components come from ``scipy.ndimage.label``.
+* :func:`line_closed_form` -- the 1-D case: R = max(L, B) with the two
+  one-sided running recurrences.
+* :func:`dilate` / :func:`is_fixed_point` -- for invariants at any size.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import ndimage
+
+
+def _lowest(dtype) -> int:
+    return int(np.iinfo(dtype).min)
+
+
+def dilate(J: np.ndarray, conn: int) -> np.ndarray:
+    """Elementary dilation by the 3x3 (8-conn) or cross (4-conn) element;
+    pixels outside the image do not take part."""
+    lo = _lowest(J.dtype)
+    H, W = J.shape
+    P = np.full((H + 2, W + 2), lo, dtype=J.dtype)
+    P[1:-1, 1:-1] = J
+    out = J.copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            if conn == 4 and dy != 0 and dx != 0:
+                continue
+            np.maximum(out, P[1 + dy:1 + dy + H, 1 + dx:1 + dx + W], out=out)
+    return out
+
+
+def brute_numpy(J: np.ndarray, I: np.ndarray, conn: int) -> np.ndarray:
+    R = J.copy()
+    while True:
+        nxt = np.minimum(dilate(R, conn), I)
+        if np.array_equal(nxt, R):
+            return R
+        R = nxt
+
+
+def is_fixed_point(R: np.ndarray, I: np.ndarray, conn: int) -> bool:
+    return bool(np.array_equal(np.minimum(dilate(R, conn), I), R))
+
+
+def threshold_decomposition(J: np.ndarray, I: np.ndarray, conn: int) -> np.ndarray:
+    structure = np.ones((3, 3), bool) if conn == 8 else ndimage.generate_binary_structure(2, 1)
+    levels = np.unique(np.concatenate([np.unique(I), np.unique(J)]))
+    R = np.full(I.shape, _lowest(I.dtype), dtype=np.int64)
+    for t in levels:  # increasing, so the last level written is the largest
+        lab, n = ndimage.label(I >= t, structure=structure)
+        if n == 0:
+            continue
+        hit = np.zeros(n + 1, bool)
+        hit[np.unique(lab[(J >= t) & (lab > 0)])] = True
+        hit[0] = False
+        R[hit[lab]] = t
+    return R.astype(I.dtype)
+
+
+def line_closed_form(J: np.ndarray, I: np.ndarray) -> np.ndarray:
+    """1-D reconstruction: L(x) = min(I(x), max(J(x), L(x-1))) from the left,
+    B the same from the right, R = max(L, B)."""
+    j = J.astype(np.int64).ravel()
+    i = I.astype(np.int64).ravel()
+    n = j.shape[0]
+    L = np.empty(n, np.int64)
+    B = np.empty(n, np.int64)
+    for x in range(n):
+        L[x] = min(i[x], max(j[x], L[x - 1])) if x else j[x]
+    for x in range(n - 1, -1, -1):
+        B[x] = min(i[x], max(j[x], B[x + 1])) if x < n - 1 else j[x]
+    return np.maximum(L, B).astype(I.dtype).reshape(J.shape)
