@@ -1,0 +1,215 @@
+/*
+ * iwpp.h -- C ABI of an MI355X (gfx950) library for grayscale morphological
+ * reconstruction by dilation, computed as an irregular wavefront propagation
+ * (IWPP): tile scans, wavefront-seed detection, queue-driven propagation to
+ * a fixed point (Gomes & Teodoro, "Efficient Execution of Irregular
+ * Wavefront Propagation Pattern on Many Integrated Core Architecture").
+ *
+ * The operation (background chapter, "Reconstrucao Morfologica", and its
+ * reconstruction Equation): given a mask I and a marker J with J <= I
+ * pixelwise, the reconstruction R_I(J) is the limit of J <- dilate_G(J) ^ I,
+ * where dilate_G takes the maximum over a pixel and its neighbours on the
+ * square grid G (4- or 8-connected, Section "Notacoes em Algoritmos
+ * Morfologicos") and ^ is the pixelwise minimum.  The result is unique.
+ *
+ * Conventions shared by every entry point:
+ *  - Images are 2-D, row-major, H rows by W columns, row pitch `ld` elements
+ *    (ld >= W; 0 means W).  Pixel (y, x) is at element y*ld + x.
+ *  - dtype IWPP_U8 (uint8, 0..255) or IWPP_I32 (int32, full range).  Paper
+ *    runs use 32-bit integers; the arithmetic is max/min/compare only, so
+ *    results are exact for both types.
+ *  - `marker` and `mask` are DEVICE pointers owned by the caller; `marker`
+ *    is overwritten with R in place (the output J of the IWPP reconstruction
+ *    algorithm).  Marker and mask must not overlap.
+ *  - Pixels outside the image do not exist (no padding value propagates).
+ *  - Every function returns an IWPP_* status code; nothing throws.  Argument
+ *    errors are detected on the host before any GPU work is queued.
+ *  - Streams are hipStream_t values passed as void*; NULL is the null stream.
+ *  - If J > I at some pixel the call reports IWPP_E_MARKER_GT_MASK; the
+ *    marker then holds R_I(min(J, I)).  With IWPP_FLAG_CLAMP_MARKER the same
+ *    result is produced and the call succeeds.
+ *  - The library keeps a workspace per (device, stream), grown on demand and
+ *    freed by iwpp_release_workspace().  Calls on one stream run in stream
+ *    order; calls on different streams may run concurrently.
+ */
+#ifndef IWPP_H
+#define IWPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define IWPP_OK 0
+#define IWPP_E_ARG (-1)             /* invalid argument (host check)        */
+#define IWPP_E_MARKER_GT_MASK (-2)  /* J > I somewhere (precondition)       */
+#define IWPP_E_NOMEM (-3)           /* device or host allocation failed     */
+#define IWPP_E_HIP (-4)             /* a HIP runtime call failed            */
+#define IWPP_E_INCOMPLETE (-5)      /* stopped at max_tile_visits; marker is
+                                       a valid partial result J <= J' <= R,
+                                       and calling again completes it      */
+#define IWPP_E_BUDGET (-6)          /* request exceeds the server budget    */
+#define IWPP_E_INTERNAL (-7)        /* a bounded device wait ran out        */
+#define IWPP_E_TIMEOUT (-8)         /* server wait timed out                */
+#define IWPP_E_UNSUPPORTED (-9)     /* parameter combination not compiled   */
+
+/* ---- element types ---- */
+#define IWPP_U8 0
+#define IWPP_I32 1
+
+/* ---- flags ---- */
+#define IWPP_FLAG_CLAMP_MARKER 1u /* use min(J, I) as the marker, no error */
+
+typedef void *iwpp_stream_t;
+
+typedef struct iwpp_image {
+  void *marker;     /* device, in/out */
+  const void *mask; /* device, in */
+  int64_t H, W;     /* rows, columns (>= 1) */
+  int64_t ld;       /* row pitch in elements; 0 means W */
+} iwpp_image;
+
+/* Work counters of the last call on a stream (or of a batch plan). */
+typedef struct iwpp_stats {
+  int32_t status;          /* IWPP_OK, _MARKER_GT_MASK, _INCOMPLETE or _INTERNAL  */
+  int32_t images;          /* images in the call                                  */
+  int64_t tiles;           /* tiles in the call                                   */
+  int64_t tile_visits;     /* tile visits (first, re-activated and re-run)        */
+  int64_t sweep_rounds;    /* rounds of the four directional passes              */
+  int64_t pixels_queued;   /* queue entries processed: the paper's "elements
+                              processed in the propagation phase"                 */
+  int64_t queue_overflows; /* tile-queue overflows (each falls back to a scan)    */
+  int64_t reprocessed;     /* tiles re-run in place after a neighbour changed     */
+  int64_t queue_high;      /* global tile-queue high-water mark                   */
+  int64_t launches;        /* kernel launches                                     */
+} iwpp_stats;
+
+/*
+ * Execution parameters.  Zero fields take the library default (or the value
+ * the autotuner stored for this problem class).
+ *   tile_h        tile height in rows: 64 or 128 (u8), 64 (i32); tiles are 64
+ *                 columns wide.
+ *   sweeps        rounds of directional passes before switching a tile to its
+ *                 queue (>= 0; -1 selects 0 explicitly).
+ *   mode          0 persistent kernel with a global tile queue (default);
+ *                 1 host-driven rounds (one launch per round, for comparison).
+ *   grid          persistent workgroups (0 = fill the device).
+ *   max_tile_visits  stop after this many tile visits (0 = no limit); used to
+ *                 test restart: the call then returns IWPP_E_INCOMPLETE.
+ *   order_seed    0: tiles start in raster order; otherwise a seeded
+ *                 permutation (results must not depend on it).
+ */
+typedef struct iwpp_params {
+  int32_t tile_h;
+  int32_t sweeps;
+  int32_t mode;
+  int32_t grid;
+  int64_t max_tile_visits;
+  uint32_t order_seed;
+  uint32_t spin_limit; /* bound on device-side waits (0 = default) */
+} iwpp_params;
+
+/* Library version, e.g. 10000 for 1.0.0. */
+int iwpp_version(void);
+
+/* Static description of a status code. */
+const char *iwpp_strerror(int code);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *iwpp_last_error(void);
+
+/*
+ * Synchronous reconstruction on the null stream (IWPP reconstruction
+ * algorithm; operation defined above).  Returns the device status.
+ */
+int iwpp_reconstruct(void *marker, const void *mask, int64_t H, int64_t W, int dtype,
+                     int conn);
+
+/*
+ * Asynchronous reconstruction of one image on `stream`.  Returns IWPP_OK once
+ * the work is queued (or a host-side argument error).  The device status and
+ * counters of the last call on that stream are read with
+ * iwpp_stream_status().  `params` may be NULL.  In mode 1 (host-driven
+ * rounds) the call synchronises the stream once per round.
+ */
+int iwpp_reconstruct_async(const iwpp_image *img, int dtype, int conn, uint32_t flags,
+                           const iwpp_params *params, iwpp_stream_t stream);
+
+/*
+ * Waits for `stream`, then returns the status of the last reconstruction
+ * queued on it and fills `stats` (may be NULL).
+ */
+int iwpp_stream_status(iwpp_stream_t stream, iwpp_stats *stats);
+
+/*
+ * Several independent images in one persistent launch (a task queue of image
+ * tiles, as in the paper's cooperative execution, "Execucao Cooperativa em
+ * Processadores Heterogeneos"): tiles of all images share one work queue and
+ * fronts never cross from one image to another.  Asynchronous like
+ * iwpp_reconstruct_async; the descriptor array is copied before returning.
+ */
+int iwpp_reconstruct_batched(const iwpp_image *imgs, int32_t n, int dtype, int conn,
+                             uint32_t flags, const iwpp_params *params,
+                             iwpp_stream_t stream);
+
+/*
+ * Reusable batch plan: descriptors, tile queue and per-tile state are
+ * allocated once; iwpp_batch_launch() re-runs the batch (with use_graph != 0
+ * the launch sequence is captured once into a HIP graph and replayed).  The
+ * images' buffers must stay valid while the plan exists.  Parameters are
+ * fixed at creation (NULL = defaults / autotuned values).
+ */
+typedef struct iwpp_batch iwpp_batch;
+int iwpp_batch_create(const iwpp_image *imgs, int32_t n, int dtype, int conn, uint32_t flags,
+                      const iwpp_params *params, iwpp_batch **out);
+int iwpp_batch_launch(iwpp_batch *b, iwpp_stream_t stream, int use_graph);
+/* Waits for the plan's last launch, returns its status and fills stats. */
+int iwpp_batch_status(iwpp_batch *b, iwpp_stats *stats);
+int iwpp_batch_destroy(iwpp_batch *b);
+
+/*
+ * Times candidate parameter sets on one image and returns the fastest in
+ * *best (bit-exactness of every candidate is the caller's to test).  The
+ * marker is left unchanged: candidates run on a scratch copy.  Results are
+ * remembered per (dtype, conn, size class) and used when params are NULL;
+ * if IWPP_TUNE_CACHE names a file, they are also stored there as JSON.
+ */
+int iwpp_autotune(const iwpp_image *img, int dtype, int conn, iwpp_stream_t stream,
+                  iwpp_params *best);
+
+/*
+ * Continuous-batching server.  Requests are admitted while the device bytes
+ * they hold (marker, mask and their share of queue and state) fit in
+ * `budget_bytes` and fewer than `max_inflight` launches are running;
+ * requests admitted together form one persistent launch, and launches of
+ * different admissions overlap on `streams` HIP streams.
+ *   submit: the image buffers are the caller's and must stay valid until
+ *           the request completes; returns IWPP_E_BUDGET if the request alone
+ *           exceeds the budget.  Non-blocking.
+ *   wait:   blocks until the request finishes (timeout_us < 0: forever) and
+ *           returns its status; latency_us receives completion - submit time.
+ */
+typedef struct iwpp_server iwpp_server;
+int iwpp_server_create(size_t budget_bytes, int dtype, int conn, int streams,
+                       int max_inflight, iwpp_server **out);
+int iwpp_server_submit(iwpp_server *s, const iwpp_image *img, uint64_t *ticket);
+int iwpp_server_wait(iwpp_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
+int iwpp_server_destroy(iwpp_server *s);
+
+/* Frees the cached per-stream workspaces (after synchronising the device). */
+int iwpp_release_workspace(void);
+
+/*
+ * Plain device-to-device streaming copy of `bytes` (a multiple of 16) with
+ * the library's own kernel: the reference for bandwidth and for scaling
+ * hardware byte counters.
+ */
+int iwpp_device_copy(void *dst, const void *src, size_t bytes, iwpp_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IWPP_H */

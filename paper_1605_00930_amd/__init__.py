@@ -1,0 +1,325 @@
+"""Python binding of the MI355X reconstruction library (``libiwpp.so``).
+
+Grayscale morphological reconstruction by dilation as an irregular wavefront
+propagation (IWPP), after Gomes & Teodoro.  Every step runs in the HIP
+kernels behind the C ABI declared in ``include/iwpp.h``; this module only
+marshals torch tensors (device memory) and streams into those calls.  There
+is no CPU fallback: if the library is not built, calls raise.
+
+Tensors are 2-D ``torch.uint8`` or ``torch.int32`` on a ROCm device with unit
+column stride; the marker is reconstructed in place.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiwpp.so")
+
+OK = 0
+E_ARG = -1
+E_MARKER_GT_MASK = -2
+E_NOMEM = -3
+E_HIP = -4
+E_INCOMPLETE = -5
+E_BUDGET = -6
+E_INTERNAL = -7
+E_TIMEOUT = -8
+E_UNSUPPORTED = -9
+U8, I32 = 0, 1
+FLAG_CLAMP_MARKER = 1
+
+
+class IwppError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = "%s (%d)" % (strerror(code) if _lib_obj else "error", code)
+        if what:
+            msg += ": " + what
+        if code == E_HIP and _lib_obj:
+            msg += ": " + _lib_obj.iwpp_last_error().decode()
+        super().__init__(msg)
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("marker", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("H", ctypes.c_int64), ("W", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("images", ctypes.c_int32),
+                ("tiles", ctypes.c_int64), ("tile_visits", ctypes.c_int64),
+                ("sweep_rounds", ctypes.c_int64), ("pixels_queued", ctypes.c_int64),
+                ("queue_overflows", ctypes.c_int64), ("reprocessed", ctypes.c_int64),
+                ("queue_high", ctypes.c_int64), ("launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tile_h", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("max_tile_visits", ctypes.c_int64), ("order_seed", ctypes.c_uint32),
+                ("spin_limit", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib_obj = None
+
+
+def _load():
+    """Load libiwpp.so (raises if it has not been built)."""
+    global _lib_obj
+    if _lib_obj is not None:
+        return _lib_obj
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libiwpp.so is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
+    P = ctypes.POINTER
+    sig = {
+        "iwpp_version": ([], i32),
+        "iwpp_strerror": ([i32], ctypes.c_char_p),
+        "iwpp_last_error": ([], ctypes.c_char_p),
+        "iwpp_reconstruct": ([vp, vp, i64, i64, i32, i32], i32),
+        "iwpp_reconstruct_async": ([P(Image), i32, i32, u32, P(Params), vp], i32),
+        "iwpp_stream_status": ([vp, P(Stats)], i32),
+        "iwpp_reconstruct_batched": ([P(Image), ctypes.c_int32, i32, i32, u32, P(Params), vp], i32),
+        "iwpp_batch_create": ([P(Image), ctypes.c_int32, i32, i32, u32, P(Params), P(vp)], i32),
+        "iwpp_batch_launch": ([vp, vp, i32], i32),
+        "iwpp_batch_status": ([vp, P(Stats)], i32),
+        "iwpp_batch_destroy": ([vp], i32),
+        "iwpp_autotune": ([P(Image), i32, i32, vp, P(Params)], i32),
+        "iwpp_server_create": ([ctypes.c_size_t, i32, i32, i32, i32, P(vp)], i32),
+        "iwpp_server_submit": ([vp, P(Image), P(ctypes.c_uint64)], i32),
+        "iwpp_server_wait": ([vp, ctypes.c_uint64, i64, P(ctypes.c_double)], i32),
+        "iwpp_server_destroy": ([vp], i32),
+        "iwpp_release_workspace": ([], i32),
+        "iwpp_device_copy": ([vp, vp, ctypes.c_size_t, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib_obj = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return _load().iwpp_strerror(code).decode()
+
+
+def version() -> int:
+    return _load().iwpp_version()
+
+
+# ---------------------------------------------------------------- marshalling
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    if t.dtype == torch.uint8:
+        return U8
+    if t.dtype == torch.int32:
+        return I32
+    raise TypeError("images must be torch.uint8 or torch.int32, got %s" % t.dtype)
+
+
+def _image(marker, mask) -> tuple[Image, int]:
+    if marker.dim() != 2 or mask.dim() != 2 or marker.shape != mask.shape:
+        raise ValueError("marker and mask must be 2-D tensors of one shape")
+    if marker.dtype != mask.dtype:
+        raise TypeError("marker and mask must share a dtype")
+    if not (marker.is_cuda and mask.is_cuda) or marker.device != mask.device:
+        raise ValueError("marker and mask must live on the same GPU")
+    if marker.stride(1) != 1 or mask.stride(1) != 1 or marker.stride(0) != mask.stride(0):
+        raise ValueError("rows must be contiguous with one common row pitch")
+    H, W = marker.shape
+    return Image(marker.data_ptr(), mask.data_ptr(), H, W, marker.stride(0)), _dtype_code(marker)
+
+
+def _stream_handle(stream) -> int | None:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _params(params) -> Params | None:
+    if params is None:
+        return None
+    if isinstance(params, Params):
+        return params
+    p = Params()
+    for k, v in dict(params).items():
+        setattr(p, k, int(v))
+    return p
+
+
+def _ptr(p):
+    return ctypes.byref(p) if p is not None else None
+
+
+# ---------------------------------------------------------------- entry points
+
+
+def reconstruct_async(marker, mask, conn: int = 8, *, clamp: bool = False, params=None,
+                      stream=None) -> None:
+    """Queue R_mask(marker) in place on `stream` (default: torch's current)."""
+    im, dt = _image(marker, mask)
+    rc = _load().iwpp_reconstruct_async(ctypes.byref(im), dt, conn,
+                                        FLAG_CLAMP_MARKER if clamp else 0,
+                                        _ptr(_params(params)), _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_reconstruct_async")
+
+
+def stream_status(stream=None, *, check: bool = True) -> dict:
+    """Wait for `stream`; status and counters of its last reconstruction."""
+    st = Stats()
+    rc = _load().iwpp_stream_status(_stream_handle(stream), ctypes.byref(st))
+    if check and rc != OK:
+        raise IwppError(rc, "reconstruction")
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def reconstruct(marker, mask, conn: int = 8, *, clamp: bool = False, params=None,
+                stream=None, check: bool = True) -> dict:
+    """Synchronous R_mask(marker) in place; returns the work counters."""
+    reconstruct_async(marker, mask, conn, clamp=clamp, params=params, stream=stream)
+    return stream_status(stream, check=check)
+
+
+def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, params=None,
+                        stream=None, check: bool = True) -> dict:
+    """Reconstruct [(marker, mask), ...] in one persistent launch."""
+    ims, dts = zip(*(_image(m, k) for m, k in pairs))
+    if len(set(dts)) != 1:
+        raise TypeError("all images of a batch must share a dtype")
+    arr = (Image * len(ims))(*ims)
+    rc = _load().iwpp_reconstruct_batched(arr, len(ims), dts[0], conn,
+                                          FLAG_CLAMP_MARKER if clamp else 0,
+                                          _ptr(_params(params)), _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_reconstruct_batched")
+    return stream_status(stream, check=check)
+
+
+class Batch:
+    """A reusable batch plan (optionally replayed as a HIP graph)."""
+
+    def __init__(self, pairs, conn: int = 8, *, clamp: bool = False, params=None):
+        ims, dts = zip(*(_image(m, k) for m, k in pairs))
+        if len(set(dts)) != 1:
+            raise TypeError("all images of a batch must share a dtype")
+        self._keep = list(pairs)
+        arr = (Image * len(ims))(*ims)
+        h = ctypes.c_void_p()
+        rc = _load().iwpp_batch_create(arr, len(ims), dts[0], conn,
+                                       FLAG_CLAMP_MARKER if clamp else 0,
+                                       _ptr(_params(params)), ctypes.byref(h))
+        if rc != OK:
+            raise IwppError(rc, "iwpp_batch_create")
+        self._h = h
+
+    def launch(self, stream=None, graph: bool = True) -> None:
+        rc = _load().iwpp_batch_launch(self._h, _stream_handle(stream), 1 if graph else 0)
+        if rc != OK:
+            raise IwppError(rc, "iwpp_batch_launch")
+
+    def status(self, check: bool = True) -> dict:
+        st = Stats()
+        rc = _load().iwpp_batch_status(self._h, ctypes.byref(st))
+        if check and rc != OK:
+            raise IwppError(rc, "batch")
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def close(self) -> None:
+        if self._h:
+            _load().iwpp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(marker, mask, conn: int = 8, stream=None) -> dict:
+    """Time parameter candidates on this image; returns the fastest set."""
+    im, dt = _image(marker, mask)
+    best = Params()
+    rc = _load().iwpp_autotune(ctypes.byref(im), dt, conn, _stream_handle(stream),
+                               ctypes.byref(best))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_autotune")
+    return best.as_dict()
+
+
+class Server:
+    """Continuous-batching request server (see iwpp_server_* in iwpp.h)."""
+
+    def __init__(self, budget_bytes: int, dtype: str = "u8", conn: int = 8, streams: int = 4,
+                 max_inflight: int = 8):
+        h = ctypes.c_void_p()
+        rc = _load().iwpp_server_create(budget_bytes, U8 if dtype == "u8" else I32, conn,
+                                        streams, max_inflight, ctypes.byref(h))
+        if rc != OK:
+            raise IwppError(rc, "iwpp_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, marker, mask) -> int:
+        im, _ = _image(marker, mask)
+        t = ctypes.c_uint64()
+        rc = _load().iwpp_server_submit(self._h, ctypes.byref(im), ctypes.byref(t))
+        if rc != OK:
+            raise IwppError(rc, "iwpp_server_submit")
+        self._keep[t.value] = (marker, mask)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> tuple[int, float]:
+        lat = ctypes.c_double()
+        rc = _load().iwpp_server_wait(self._h, ticket, timeout_us, ctypes.byref(lat))
+        if rc != E_TIMEOUT:
+            self._keep.pop(ticket, None)
+        return rc, lat.value
+
+    def close(self) -> None:
+        if self._h:
+            _load().iwpp_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_copy(dst, src, stream=None) -> None:
+    """The library's plain streaming copy kernel (bandwidth reference)."""
+    n = src.numel() * src.element_size()
+    rc = _load().iwpp_device_copy(dst.data_ptr(), src.data_ptr(), n, _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_device_copy")
+
+
+def release_workspace() -> None:
+    rc = _load().iwpp_release_workspace()
+    if rc != OK:
+        raise IwppError(rc, "iwpp_release_workspace")

@@ -1,0 +1,56 @@
+// iwpp_runtime.h -- host-side pieces shared by the C-ABI implementation files
+// (iwpp_api.cpp, iwpp_server.cpp).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "iwpp.h"
+#include "iwpp_internal.h"
+
+namespace iwpp {
+
+// Parameters after defaults, tuned values and user overrides.
+struct Resolved {
+  int tile_h;
+  int sweeps;
+  int mode;
+  int grid;
+  int64_t max_visits;
+  uint32_t order_seed;
+  uint32_t spin_limit;
+};
+
+// Device buffers of one launch context (a stream workspace, a batch plan or a
+// server slot).  Grown on demand; release() frees everything.
+struct Buffers {
+  DevCtl* ctl = nullptr;
+  DevCtl* host_ctl = nullptr;  // pinned copy of the control block
+  int* queue = nullptr;
+  uint32_t* state = nullptr;
+  uint8_t* visited = nullptr;
+  uint8_t* act[2] = {nullptr, nullptr};
+  DevImage* descs = nullptr;
+  int64_t tiles_cap = 0;
+  int64_t act_cap = 0;
+  uint32_t qcap_cap = 0;
+  int descs_cap = 0;
+  hipStream_t stream_owner = nullptr;
+  bool incomplete_rounds = false;
+  int ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds);
+  void release();
+};
+
+Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W);
+int check_params(const iwpp_params* p);
+int check_image(const iwpp_image* im, int dtype);
+int check_common(int dtype, int conn, uint32_t flags);
+DevImage make_dev_image(const iwpp_image& im, int tile_h, int64_t tile_base);
+int device_grid(const Variant& v, int64_t ntiles, int want, int* grid);
+int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& one,
+            const DevImage* d_imgs, int nimg, int64_t ntiles, hipStream_t st, int64_t* launches);
+int status_of(const DevCtl& c, uint32_t flags, bool incomplete_rounds);
+void fill_stats(const DevCtl& c, int status, int nimg, int64_t ntiles, int64_t launches,
+                iwpp_stats* s);
+
+}  // namespace iwpp

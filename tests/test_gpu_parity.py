@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality.  Inputs come from the seeded
+generators in ``synth``; expected values only ever come from ``oracle``.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def iwpp():
+    import torch
+
+    import paper_1605_00930_amd as lib
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib._load()
+    return lib
+
+
+def run(iwpp, I, J, conn=8, ld_pad=0, check=True, **kw):
+    import torch
+
+    dev = torch.device("cuda:0")
+    H, W = I.shape
+    if ld_pad:
+        bigJ = torch.zeros((H, W + ld_pad), dtype=torch.from_numpy(J).dtype, device=dev)
+        bigI = torch.zeros_like(bigJ)
+        bigJ[:, :W] = torch.from_numpy(J).to(dev)
+        bigI[:, :W] = torch.from_numpy(I).to(dev)
+        Jt, It = bigJ[:, :W], bigI[:, :W]
+    else:
+        Jt = torch.from_numpy(np.ascontiguousarray(J)).to(dev)
+        It = torch.from_numpy(np.ascontiguousarray(I)).to(dev)
+    st = iwpp.reconstruct(Jt, It, conn, check=check, **kw)
+    return Jt.cpu().numpy(), st
+
+
+def expect(I, J, conn, clamp=False):
+    rc, R = oracle.reconstruct(J, I, conn, clamp=clamp)
+    assert rc == oracle.OK
+    return R
+
+
+def same(got, want, label=""):
+    if not np.array_equal(got, want):
+        bad = np.argwhere(got != want)
+        y, x = bad[0]
+        raise AssertionError("%s: %d pixels differ, first at (%d, %d): got %d want %d"
+                             % (label, len(bad), y, x, got[y, x], want[y, x]))
+
+
+def announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ small
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_c1_full_size(iwpp, conn):
+    I, J = synth.c1()
+    announce("c1 512x512 u8 conn %d" % conn)
+    got, st = run(iwpp, I, J, conn)
+    same(got, expect(I, J, conn), "c1")
+    assert st["tile_visits"] >= st["tiles"]
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fill_holes_scaled(iwpp, conn):
+    I, J = synth.c2(H=1000, W=777)
+    announce("c2-scaled 1000x777 u8 conn %d" % conn)
+    got, _ = run(iwpp, I, J, conn)
+    same(got, expect(I, J, conn), "c2-scaled")
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_smooth_i32_scaled(iwpp, conn):
+    I, J = synth.c3_i32(H=700, W=900)
+    announce("c3-i32-scaled 700x900 conn %d" % conn)
+    got, _ = run(iwpp, I, J, conn)
+    same(got, expect(I, J, conn), "c3-i32-scaled")
+
+
+SIZES = [(1, 1), (1, 200), (200, 1), (2, 3), (63, 63), (64, 64), (65, 65), (127, 129),
+         (128, 128), (129, 127), (97, 211), (257, 61), (13, 640)]
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.int32])
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fuzz_shapes(iwpp, dtype, conn):
+    rng = np.random.default_rng(100 + conn + (dtype == np.int32))
+    for (H, W) in SIZES:
+        for kind in ("uniform", "sparse", "plateau", "extreme"):
+            I, J = synth.random_pair(rng, H, W, dtype, kind,
+                                     levels=8 if kind == "uniform" else None)
+            announce("fuzz %dx%d %s %s conn %d" % (H, W, np.dtype(dtype).name, kind, conn))
+            got, _ = run(iwpp, I, J, conn)
+            same(got, expect(I, J, conn), "fuzz %dx%d %s" % (H, W, kind))
+
+
+def test_row_pitch(iwpp):
+    I, J = synth.c2(H=300, W=250)
+    announce("pitch 300x250 ld=250+37")
+    got, _ = run(iwpp, I, J, 8, ld_pad=37)
+    same(got, expect(I, J, 8), "pitched")
+
+
+# ------------------------------------------------------------------ parameters
+
+
+@pytest.mark.parametrize("params", [
+    {"mode": 1}, {"sweeps": -1}, {"sweeps": 1}, {"sweeps": 4}, {"tile_h": 128},
+    {"order_seed": 7}, {"order_seed": 12345, "sweeps": -1}, {"grid": 3}, {"grid": 1},
+    {"mode": 1, "sweeps": -1}, {"mode": 1, "tile_h": 128},
+])
+def test_parameters_do_not_change_the_result(iwpp, params):
+    for (I, J, conn) in [(*synth.c2(H=600, W=520), 8), (*synth.c1(H=400, W=333), 4)]:
+        if params.get("tile_h") == 128 and I.dtype != np.uint8:
+            continue
+        announce("params %s %dx%d conn %d" % (params, I.shape[0], I.shape[1], conn))
+        got, _ = run(iwpp, I, J, conn, params=params)
+        same(got, expect(I, J, conn), "params %s" % params)
+    I, J = synth.c3_i32(H=300, W=450)
+    if params.get("tile_h") != 128:
+        announce("params %s i32 300x450" % (params,))
+        got, _ = run(iwpp, I, J, 8, params=params)
+        same(got, expect(I, J, 8), "params %s i32" % params)
+
+
+# ------------------------------------------------------------------ errors / restart
+
+
+def test_marker_above_mask(iwpp):
+    I, J = synth.c1(H=200, W=150)
+    J = J.copy()
+    J[50, 60] = 255
+    J[199, 149] = 255
+    I[199, 149] = 3
+    announce("marker>mask error path")
+    got, st = run(iwpp, I, J, 8, check=False)
+    assert st["rc"] == iwpp.E_MARKER_GT_MASK
+    got, st = run(iwpp, I, J, 8, clamp=True)
+    assert st["rc"] == iwpp.OK
+    same(got, expect(I, J, 8, clamp=True), "clamped")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_restart_from_partial_result(iwpp, mode):
+    import torch
+
+    I, J = synth.c2(H=700, W=640)
+    R = expect(I, J, 8)
+    dev = torch.device("cuda:0")
+    Jt = torch.from_numpy(J).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    announce("restart mode %d" % mode)
+    st = iwpp.reconstruct(Jt, It, 8, params={"max_tile_visits": 20, "mode": mode}, check=False)
+    assert st["rc"] == iwpp.E_INCOMPLETE
+    part = Jt.cpu().numpy()
+    assert (J <= part).all() and (part <= R).all()
+    st = iwpp.reconstruct(Jt, It, 8, params={"mode": mode})
+    same(Jt.cpu().numpy(), R, "restarted")
+
+
+def test_stats_report_work(iwpp):
+    I, J = synth.c2(H=512, W=512)
+    announce("stats")
+    _, st = run(iwpp, I, J, 8)
+    assert st["tiles"] == 8 * 8
+    assert st["tile_visits"] >= st["tiles"]
+    assert st["pixels_queued"] >= 0 and st["sweep_rounds"] > 0
+    assert st["launches"] >= 2
+
+
+# ------------------------------------------------------------------ batched
+
+
+def test_batched_uneven_sizes(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    batch = synth.c4(n=12, lo=40, hi=700)
+    pairs = [(torch.from_numpy(J).to(dev), torch.from_numpy(I).to(dev)) for I, J in batch]
+    announce("batched 12 images")
+    st = iwpp.reconstruct_batched(pairs, 8)
+    assert st["images"] == 12
+    for k, (I, J) in enumerate(batch):
+        same(pairs[k][0].cpu().numpy(), expect(I, J, 8), "batched image %d" % k)
+
+
+def test_batch_plan_graph_replays(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    batch = synth.c4(n=9, lo=64, hi=500)
+    batch.append(synth.c2(H=300, W=301))
+    pristine = [torch.from_numpy(J).to(dev) for I, J in batch]
+    pairs = [(p.clone(), torch.from_numpy(I).to(dev)) for p, (I, J) in zip(pristine, batch)]
+    want = [expect(I, J, 8) for I, J in batch]
+    plan = iwpp.Batch(pairs, 8)
+    stream = torch.cuda.Stream()
+    for rep in range(4):
+        announce("graph replay %d" % rep)
+        with torch.cuda.stream(stream):
+            for (m, _), p in zip(pairs, pristine):
+                m.copy_(p)
+        plan.launch(stream=stream, graph=rep % 2 == 0 or rep == 3)
+        st = plan.status()
+        torch.cuda.synchronize()
+        for k in range(len(batch)):
+            same(pairs[k][0].cpu().numpy(), want[k], "replay %d image %d" % (rep, k))
+        assert st["images"] == len(batch)
+    plan.close()
+
+
+# ------------------------------------------------------------------ full sizes
+
+
+def test_c2_full_size_bit_exact(iwpp):
+    I, J = synth.c2()
+    announce("c2 full 4096x4096 u8 conn 8")
+    got, st = run(iwpp, I, J, 8)
+    same(got, expect(I, J, 8), "c2 full")
