@@ -1,0 +1,344 @@
+"""Benchmark: grayscale reconstruction by dilation on one MI355X.
+
+Contract: ``python bench.py --gpus N --steps K --warmup W`` prints ONE JSON
+line.  A step is one whole reconstruction (all tiles, scans, seed detection,
+queue propagation, cross-tile fixed point) of one synthetic workload whose
+inputs are already resident in HBM.  Before each step the marker is restored
+from a pristine device copy; that copy is not part of the step's timed
+region (hipEvents around the library call on the bench's stream).
+
+Workloads (--workload):
+  c2     4096x4096 uint8 tissue-like ellipses, fill-holes marker (default)
+  c1     512x512 uint8 Gaussian blobs, h-dome marker (latency bound)
+  c3u8   32768x32768 uint8 ellipses, fill-holes marker
+  c3i32  32768x32768 int32 smooth field, h-dome marker I - 4096
+  c4     256 images, sides log-uniform 512..4096, one batched launch
+         (HIP graph) vs the per-image loop
+  c5     served stream: Poisson arrivals at 2000 req/s into the
+         continuous-batching server
+
+Extras in the JSON line:
+  roofline      for the dominant kernel (the persistent tile kernel):
+                algorithmic bytes 3*sizeof(T) per pixel per launch over its
+                hipEvent-measured duration, against 8 TB/s; `traffic` from the
+                committed rocprofv3 counter summary when it matches the
+                current kernel source, else null.
+  cpu_baseline  the CPU oracle (sequential C) timed on this host on a bounded
+                sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s reconstruction (bit-exact) + % HBM roofline; batched p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1605_00930_amd", "csrc", "iwpp_kernels.hip")
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch from profiles/pmc_<workload>.txt, or None if the
+    summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_workload(name: str, scale: int = 1):
+    import synth
+
+    if name == "c1":
+        return [synth.c1()], "u8", "512x512 u8 gaussian blobs, h-dome h=40, 8-conn"
+    if name == "c2":
+        return [synth.c2()], "u8", "4096x4096 u8 ellipses (3000), fill-holes frame marker, 8-conn"
+    if name == "c3u8":
+        n = 32768 // scale
+        return [synth.c3_u8(H=n, W=n)], "u8", "%dx%d u8 ellipses, fill-holes frame marker, 8-conn" % (n, n)
+    if name == "c3i32":
+        n = 32768 // scale
+        return [synth.c3_i32(H=n, W=n)], "i32", "%dx%d i32 9x9-box field, h-dome h=4096, 8-conn" % (n, n)
+    if name == "c4":
+        return synth.c4(), "u8", "256 u8 images, sides log-uniform 512..4096, h-dome h~U{10..80}, 8-conn"
+    raise ValueError(name)
+
+
+def cpu_baseline(name: str, budget_s: float = 20.0):
+    """Time the oracle (single thread) on a bounded sample of the workload."""
+    import oracle
+    import synth
+
+    if name == "c1":
+        pairs = [synth.c1()]
+        sample = "full 512x512 image"
+    elif name == "c2":
+        pairs = [synth.c2()]
+        sample = "full 4096x4096 image"
+    elif name == "c3u8":
+        pairs = [synth.c3_u8(H=8192, W=8192)]
+        sample = "8192x8192 image of the same recipe (ellipse count scaled by area)"
+    elif name == "c3i32":
+        pairs = [synth.c3_i32(H=8192, W=8192)]
+        sample = "8192x8192 image of the same recipe"
+    elif name in ("c4", "c5"):
+        pairs = synth.c4(n=24)
+        sample = "first 24 images of the batch recipe"
+    else:
+        raise ValueError(name)
+    px = 0
+    t = 0.0
+    runs = 0
+    while t < budget_s and runs < 10:
+        for I, J in pairs:
+            t0 = time.perf_counter()
+            rc, _ = oracle.reconstruct(J, I, 8)
+            t += time.perf_counter() - t0
+            assert rc == 0
+            px += I.size
+        runs += 1
+    return {"value": round(px / t / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": "%s, %d run(s), %.1f s of CPU time" % (sample, runs, t)}
+
+
+def bench_single(args, torch, iwpp):
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    pairs, dt, desc = make_workload(args.workload, args.scale)
+    log("generated %s in %.1f s" % (args.workload, time.perf_counter() - t0))
+    (I, J), = pairs
+    H, W = I.shape
+    Jt0 = torch.from_numpy(J).to(dev)
+    It = torch.from_numpy(I).to(dev)
+    del pairs, I, J
+    Jt = torch.empty_like(Jt0)
+    stream = torch.cuda.Stream()
+    params = {"timing": 1}
+    for k in ("tile_h", "sweeps", "mode", "seed_queue"):
+        v = getattr(args, k)
+        if v is not None:
+            params[k] = v
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    call_ms, kern_ms, stats = [], [], None
+    torch.cuda.synchronize()
+    for step in range(args.warmup + args.steps):
+        if step == args.warmup:
+            torch.cuda.synchronize()
+            t_wall0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            Jt.copy_(Jt0)
+            ev0.record(stream)
+            iwpp.reconstruct_async(Jt, It, 8, params=params, stream=stream)
+            ev1.record(stream)
+        st = iwpp.stream_status(stream)
+        log("step %d: %.3f ms (kernel %.3f ms, visits %d)"
+            % (step, ev0.elapsed_time(ev1), st["kernel_ms"], st["tile_visits"]))
+        if step >= args.warmup:
+            call_ms.append(ev0.elapsed_time(ev1))
+            kern_ms.append(st["kernel_ms"])
+            stats = st
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    es = 1 if dt == "u8" else 4
+    ms = float(np.mean(call_ms))
+    kms = float(np.mean(kern_ms))
+    px = H * W
+    achieved = 3 * es * px / (kms * 1e-3) / 1e9
+    traffic = load_traffic(args.workload)
+    res = {
+        "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": desc, "H": H, "W": W, "conn": 8,
+                   "params": {k: v for k, v in params.items() if k != "timing"}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_persistent (tile worker)", "kernel_ms": round(kms, 4),
+                     "algorithmic_bytes_per_launch": 3 * es * px},
+        "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
+                                             "pixels_queued", "queue_overflows", "reprocessed",
+                                             "queue_iterations", "idle_ms", "load_ms", "solve_ms",
+                                             "store_ms")},
+        "ms_min": round(float(np.min(call_ms)), 4), "ms_cv": round(float(np.std(call_ms) / ms), 4),
+        "wall_ms_per_step_incl_restore": round(wall * 1e3 / args.steps, 4),
+    }
+    return res
+
+
+def bench_batched(args, torch, iwpp):
+    dev = torch.device("cuda:0")
+    pairs, dt, desc = make_workload("c4")
+    pristine = [torch.from_numpy(J).to(dev) for I, J in pairs]
+    masks = [torch.from_numpy(I).to(dev) for I, J in pairs]
+    px = sum(I.size for I, J in pairs)
+    del pairs
+    work = [p.clone() for p in pristine]
+    stream = torch.cuda.Stream()
+    params = {"timing": 1}
+    if args.tile_h:
+        params["tile_h"] = args.tile_h
+    if args.sweeps is not None:
+        params["sweeps"] = args.sweeps
+    plan = iwpp.Batch(list(zip(work, masks)), 8, params=params)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    times, kern = [], []
+    torch.cuda.synchronize()
+    for step in range(args.warmup + args.steps):
+        if step == args.warmup:
+            torch.cuda.synchronize()
+            t_wall0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for w, p in zip(work, pristine):
+                w.copy_(p)
+            ev0.record(stream)
+        plan.launch(stream=stream, graph=True)
+        with torch.cuda.stream(stream):
+            ev1.record(stream)
+        st = plan.status()
+        log("step %d: %.3f ms (kernel %.3f ms)" % (step, ev0.elapsed_time(ev1), st["kernel_ms"]))
+        if step >= args.warmup:
+            times.append(ev0.elapsed_time(ev1))
+            kern.append(st["kernel_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    plan.close()
+    # the plain per-image path on the same GPU, for comparison
+    per_image = []
+    lat = []
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            for w, p in zip(work, pristine):
+                w.copy_(p)
+            ev0.record(stream)
+        for w, m in zip(work, masks):
+            e_a = torch.cuda.Event(enable_timing=True)
+            e_b = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                e_a.record(stream)
+            iwpp.reconstruct_async(w, m, 8, params={k: v for k, v in params.items() if k != "timing"},
+                                   stream=stream)
+            with torch.cuda.stream(stream):
+                e_b.record(stream)
+            if rep == 1:
+                lat.append((e_a, e_b))
+        with torch.cuda.stream(stream):
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        if rep == 1:
+            per_image.append(ev0.elapsed_time(ev1))
+    lats = sorted(a.elapsed_time(b) for a, b in lat)
+    ms = float(np.mean(times))
+    kms = float(np.mean(kern))
+    achieved = 3 * px / (kms * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+        "data": "synthetic",
+        "config": {"workload": "c4", "desc": desc, "images": len(pristine), "pixels": px,
+                   "conn": 8, "graph": True},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("c4"), "kernel": "k_persistent (tile worker)",
+                     "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": 3 * px},
+        "per_image_loop": {"ms": round(per_image[0], 4),
+                           "value": round(px / (per_image[0] * 1e-3) / 1e6, 2),
+                           "image_ms_p50": round(lats[len(lats) // 2], 4),
+                           "image_ms_p99": round(lats[min(len(lats) - 1, int(0.99 * len(lats)))], 4)},
+        "batched_speedup_vs_loop": round(per_image[0] / ms, 3),
+        "wall_ms_per_step_incl_restore": round(wall * 1e3 / args.steps, 4),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3u8", "c3i32", "c4", "c5"])
+    ap.add_argument("--scale", type=int, default=1, help="divide the 32K side (c3*) by this")
+    ap.add_argument("--tile-h", dest="tile_h", type=int, default=None)
+    ap.add_argument("--sweeps", type=int, default=None)
+    ap.add_argument("--mode", type=int, default=None)
+    ap.add_argument("--seed-queue", dest="seed_queue", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run the library copy kernel on this many MiB (profiler scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1605_00930_amd as iwpp
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if not os.path.exists(iwpp.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    iwpp._load()
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            iwpp.device_copy(b, a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if args.workload == "c4":
+        res = bench_batched(args, torch, iwpp)
+    elif args.workload == "c5":
+        import serve
+
+        res = serve.bench_served(args, torch, iwpp, METRIC)
+    else:
+        res = bench_single(args, torch, iwpp)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+    res["kernel_source_sha256"] = kernel_source_hash()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

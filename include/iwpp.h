@@ -83,15 +83,21 @@ typedef struct iwpp_stats {
                               processed in the propagation phase"                 */
   int64_t queue_overflows; /* tile-queue overflows (each falls back to a scan)    */
   int64_t reprocessed;     /* tiles re-run in place after a neighbour changed     */
-  int64_t queue_high;      /* global tile-queue high-water mark                   */
+  int64_t requeued;        /* tiles put back on a work queue after their first visit */
   int64_t launches;        /* kernel launches                                     */
+  double kernel_ms;        /* device time of the reconstruction kernels when
+                              iwpp_params.timing was set, else 0                  */
+  int64_t queue_iterations; /* identify/propagate pairs over all tile queues      */
+  /* wavefront-milliseconds summed over the persistent workers: waiting for a
+     tile, loading tiles, solving them, storing and publishing them */
+  double idle_ms, load_ms, solve_ms, store_ms;
 } iwpp_stats;
 
 /*
  * Execution parameters.  Zero fields take the library default (or the value
  * the autotuner stored for this problem class).
- *   tile_h        tile height in rows: 64 or 128 (u8), 64 (i32); tiles are 64
- *                 columns wide.
+ *   tile_h        tile height in rows: 64 or 128 (u8), 32 or 64 (i32); tiles
+ *                 are 64 columns wide, one wavefront per tile.
  *   sweeps        rounds of directional passes before switching a tile to its
  *                 queue (>= 0; -1 selects 0 explicitly).
  *   mode          0 persistent kernel with a global tile queue (default);
@@ -101,6 +107,12 @@ typedef struct iwpp_stats {
  *                 test restart: the call then returns IWPP_E_INCOMPLETE.
  *   order_seed    0: tiles start in raster order; otherwise a seeded
  *                 permutation (results must not depend on it).
+ *   timing        non-zero: bracket the reconstruction kernels with HIP
+ *                 events on the call's stream; iwpp_stats.kernel_ms then
+ *                 reports their device time.
+ *   seed_queue    a re-visited tile whose new halo can raise at most this
+ *                 many border pixels goes straight to its queue; more start
+ *                 with a scan round (0 = default 32, -1 = always scan).
  */
 typedef struct iwpp_params {
   int32_t tile_h;
@@ -110,6 +122,8 @@ typedef struct iwpp_params {
   int64_t max_tile_visits;
   uint32_t order_seed;
   uint32_t spin_limit; /* bound on device-side waits (0 = default) */
+  int32_t timing;
+  int32_t seed_queue;
 } iwpp_params;
 
 /* Library version, e.g. 10000 for 1.0.0. */

@@ -52,17 +52,22 @@ class Stats(ctypes.Structure):
                 ("tiles", ctypes.c_int64), ("tile_visits", ctypes.c_int64),
                 ("sweep_rounds", ctypes.c_int64), ("pixels_queued", ctypes.c_int64),
                 ("queue_overflows", ctypes.c_int64), ("reprocessed", ctypes.c_int64),
-                ("queue_high", ctypes.c_int64), ("launches", ctypes.c_int64)]
+                ("requeued", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double), ("queue_iterations", ctypes.c_int64),
+                ("idle_ms", ctypes.c_double), ("load_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("store_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float if t is ctypes.c_double else int)(getattr(self, k))
+                for k, t in self._fields_}
 
 
 class Params(ctypes.Structure):
     _fields_ = [("tile_h", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("max_tile_visits", ctypes.c_int64), ("order_seed", ctypes.c_uint32),
-                ("spin_limit", ctypes.c_uint32)]
+                ("spin_limit", ctypes.c_uint32), ("timing", ctypes.c_int32),
+                ("seed_queue", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -118,7 +118,11 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   r.max_visits = 0;
   r.order_seed = 0;
   r.spin_limit = 1u << 24;
+  r.timing = 0;
+  r.seed_queue_max = 32;
   if (user) {
+    r.timing = user->timing;
+    if (user->seed_queue) r.seed_queue_max = user->seed_queue < 0 ? 0 : user->seed_queue;
     if (user->tile_h) r.tile_h = user->tile_h;
     if (user->sweeps) r.sweeps = user->sweeps < 0 ? 0 : user->sweeps;
     if (user->mode) r.mode = user->mode;
@@ -132,7 +136,8 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
 
 int check_params(const iwpp_params* p) {
   if (!p) return IWPP_OK;
-  if (p->tile_h != 0 && p->tile_h != 64 && p->tile_h != 128) return IWPP_E_ARG;
+  if (p->tile_h != 0 && p->tile_h != 32 && p->tile_h != 64 && p->tile_h != 128)
+    return IWPP_E_ARG;
   if (p->sweeps < -1 || p->sweeps > 64) return IWPP_E_ARG;
   if (p->mode != 0 && p->mode != 1) return IWPP_E_ARG;
   if (p->grid < 0 || p->max_tile_visits < 0) return IWPP_E_ARG;
@@ -186,11 +191,28 @@ void order_for(uint32_t seed, int64_t ntiles, uint32_t* mul, uint32_t* add) {
       b = t;
     }
     if (a == 1 && p % (uint64_t)ntiles != 0) {
-      *mul = p;
+      *mul = (uint32_t)(p % (uint64_t)ntiles);
       break;
     }
   }
   *add = (uint32_t)(((uint64_t)seed * 2654435761u) % (uint64_t)ntiles);
+}
+
+// Queue chunking: consecutive tile ids form chunks dealt round-robin to the
+// per-XCD queues.  A single image uses bands of whole tile rows (up to four
+// rows, at least four bands per queue when the image is tall enough); a
+// batch uses short runs so that every queue gets a share of every image.
+int64_t queue_chunk(int64_t ntiles, int nq, int nimg, int64_t tiles_x, int64_t tiles_y) {
+  if (nimg == 1) {
+    int64_t bh = tiles_y / (4 * (int64_t)nq);
+    if (bh < 1) bh = 1;
+    if (bh > 4) bh = 4;
+    return bh * tiles_x;
+  }
+  int64_t c = ntiles / (8 * (int64_t)nq);
+  if (c < 1) c = 1;
+  if (c > 64) c = 64;
+  return c;
 }
 
 int device_grid(const Variant& v, int64_t ntiles, int want, int* grid) {
@@ -271,6 +293,8 @@ int Buffers::ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds) {
 }
 
 void Buffers::release() {
+  if (ev[0]) (void)hipEventDestroy(ev[0]);
+  if (ev[1]) (void)hipEventDestroy(ev[1]);
   (void)hipFree(ctl);
   (void)hipHostFree(host_ctl);
   (void)hipFree(queue);
@@ -280,6 +304,21 @@ void Buffers::release() {
   (void)hipFree(act[1]);
   (void)hipFree(descs);
   *this = Buffers{};
+}
+
+// Grid, queue count, chunk and ring capacity of a persistent launch.
+int plan_queues(const Variant& v, const Resolved& rp, int64_t ntiles, int nimg,
+                const DevImage& one, int* grid, KParams* kp) {
+  int rc = device_grid(v, ntiles, rp.grid, grid);
+  if (rc) return rc;
+  kp->nq = *grid < kMaxQueues ? *grid : kMaxQueues;
+  kp->chunk = (int32_t)queue_chunk(ntiles, kp->nq, nimg, one.tiles_x, one.tiles_y);
+  const int64_t nchunks = (ntiles + kp->chunk - 1) / kp->chunk;
+  const int64_t per_q = (nchunks + kp->nq - 1) / kp->nq * kp->chunk;
+  const int64_t qcap = per_q + *grid + 64;
+  if (qcap * kp->nq >= (int64_t(1) << 31)) return IWPP_E_ARG;
+  kp->qcap = (uint32_t)qcap;
+  return IWPP_OK;
 }
 
 // Enqueue one reconstruction of `nimg` images (descriptors either `one` or a
@@ -293,36 +332,59 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
   kp.ntiles = ntiles;
   kp.max_visits = rp.max_visits;
   kp.spin_limit = rp.spin_limit;
+  kp.seed_queue_max = rp.seed_queue_max;
   int64_t nl = 0;
   if (rp.mode == 0) {
     int grid = 0;
-    int rc = device_grid(v, ntiles, rp.grid, &grid);
+    int rc = plan_queues(v, rp, ntiles, nimg, one, &grid, &kp);
     if (rc) return rc;
-    const uint64_t qcap = (uint64_t)ntiles + (uint64_t)grid + 64;
-    if (qcap >= (1ull << 31)) return IWPP_E_ARG;
-    kp.qcap = (uint32_t)qcap;
-    rc = b.ensure(ntiles, kp.qcap, nimg, false);
+    rc = b.ensure(ntiles, kp.qcap * (uint32_t)kp.nq, nimg, false);
     if (rc) return rc;
-    uint32_t mul, add;
-    order_for(rp.order_seed, ntiles, &mul, &add);
-    HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, mul, add, st));
+    order_for(rp.order_seed, ntiles, &kp.order_mul, &kp.order_add);
+    HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, st));
+    b.timed = false;
+    if (rp.timing) {
+      if (!b.ev[0]) HIP_TRY(hipEventCreate(&b.ev[0]));
+      if (!b.ev[1]) HIP_TRY(hipEventCreate(&b.ev[1]));
+      HIP_TRY(hipEventRecord(b.ev[0], st));
+    }
     HIP_TRY(launch_persistent(v, one, d_imgs, kp, b.ctl, b.queue, b.state, b.visited, grid, st));
+    if (rp.timing) {
+      HIP_TRY(hipEventRecord(b.ev[1], st));
+      b.timed = true;
+    }
     nl = 2;
   } else {
     kp.qcap = 0;
+    kp.nq = 1;
+    kp.chunk = 1;
+    kp.order_mul = 1;
     int rc = b.ensure(ntiles, 0, nimg, true);
     if (rc) return rc;
-    HIP_TRY(launch_init(kp, b.ctl, nullptr, nullptr, b.visited, b.act[0], 1, 0, st));
+    HIP_TRY(launch_init(kp, b.ctl, nullptr, nullptr, b.visited, b.act[0], st));
     nl = 1;
     int cur = 0;
+    b.timed = false;
+    b.rounds_ms = 0;
+    if (rp.timing) {
+      if (!b.ev[0]) HIP_TRY(hipEventCreate(&b.ev[0]));
+      if (!b.ev[1]) HIP_TRY(hipEventCreate(&b.ev[1]));
+    }
     for (int64_t round = 0;; ++round) {
       HIP_TRY(launch_clear_round(b.ctl, st));
       kp.first_round = round == 0;
+      if (rp.timing) HIP_TRY(hipEventRecord(b.ev[0], st));
       HIP_TRY(launch_round(v, one, d_imgs, kp, b.ctl, b.act[cur], b.act[cur ^ 1], b.visited, st));
+      if (rp.timing) HIP_TRY(hipEventRecord(b.ev[1], st));
       nl += 2;
       HIP_TRY(hipMemcpyAsync(b.host_ctl, b.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
-      if (!b.host_ctl->active_any || (b.host_ctl->status & ST_INTERNAL)) break;
+      if (rp.timing) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, b.ev[0], b.ev[1]));
+        b.rounds_ms += ms;
+      }
+      if (!b.host_ctl->active_any || (b.host_ctl->status.v & ST_INTERNAL)) break;
       if (rp.max_visits > 0 && (int64_t)b.host_ctl->visits >= rp.max_visits) {
         // stop between rounds: the marker holds a valid partial result
         b.incomplete_rounds = true;
@@ -342,9 +404,10 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
 }
 
 int status_of(const DevCtl& c, uint32_t flags, bool incomplete_rounds) {
-  if (c.status & ST_INTERNAL) return IWPP_E_INTERNAL;
-  if ((c.status & ST_INCOMPLETE) || incomplete_rounds) return IWPP_E_INCOMPLETE;
-  if ((c.status & ST_MARKER_GT_MASK) && !(flags & IWPP_FLAG_CLAMP_MARKER))
+  const uint32_t st = c.status.v;
+  if (st & ST_INTERNAL) return IWPP_E_INTERNAL;
+  if ((st & ST_INCOMPLETE) || incomplete_rounds) return IWPP_E_INCOMPLETE;
+  if ((st & ST_MARKER_GT_MASK) && !(flags & IWPP_FLAG_CLAMP_MARKER))
     return IWPP_E_MARKER_GT_MASK;
   return IWPP_OK;
 }
@@ -361,8 +424,29 @@ void fill_stats(const DevCtl& c, int status, int nimg, int64_t ntiles, int64_t l
   s->pixels_queued = (int64_t)c.pushes;
   s->queue_overflows = (int64_t)c.overflows;
   s->reprocessed = (int64_t)c.reproc;
-  s->queue_high = (int64_t)c.q_high;
+  s->requeued = (int64_t)c.requeued;
   s->launches = launches;
+  s->queue_iterations = (int64_t)c.qiters;
+  int khz = 100000;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  (void)hipGetLastError();
+  s->idle_ms = (double)c.t_idle / khz;
+  s->load_ms = (double)c.t_load / khz;
+  s->solve_ms = (double)c.t_solve / khz;
+  s->store_ms = (double)c.t_store / khz;
+}
+
+double kernel_ms(Buffers& b) {
+  if (b.timed) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, b.ev[0], b.ev[1]) == hipSuccess) return ms;
+    (void)hipGetLastError();  // do not leave a stale error for the caller's next launch
+    return 0;
+  }
+  return b.rounds_ms;
 }
 
 }  // namespace iwpp
@@ -459,6 +543,7 @@ int iwpp_stream_status(iwpp_stream_t stream, iwpp_stats* stats) {
   const DevCtl c = *w->buf.host_ctl;
   const int status = status_of(c, w->flags, w->buf.incomplete_rounds);
   fill_stats(c, status, w->nimg, w->ntiles, w->launches, stats);
+  if (stats) stats->kernel_ms = kernel_ms(w->buf);
   return status;
 }
 
@@ -577,9 +662,10 @@ int iwpp_batch_create(const iwpp_image* imgs, int32_t n, int dtype, int conn, ui
   b->ntiles = base;
   hipError_t e = hipGetDevice(&b->device);
   int grid = 0;
-  if (e == hipSuccess) rc = device_grid(b->v, base, b->rp.grid, &grid);
-  else rc = hip_fail(e, "hipGetDevice");
-  if (!rc) rc = b->buf.ensure(base, (uint32_t)(base + grid + 64), n, false);
+  if (e != hipSuccess) rc = hip_fail(e, "hipGetDevice");
+  KParams kp{};
+  if (!rc) rc = plan_queues(b->v, b->rp, base, n, b->h[0], &grid, &kp);
+  if (!rc) rc = b->buf.ensure(base, kp.qcap * (uint32_t)kp.nq, n, false);
   if (!rc) {
     e = hipMemcpy(b->buf.descs, b->h.data(), n * sizeof(DevImage), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(descs)");
@@ -609,12 +695,14 @@ int iwpp_batch_launch(iwpp_batch* b, iwpp_stream_t stream, int use_graph) {
     HIP_TRY(hipStreamCreateWithFlags(&b->graph_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->graph_stream, hipStreamCaptureModeThreadLocal));
     int64_t nl = 0;
-    int rc = enqueue(b->buf, b->v, b->rp, b->h[0], b->buf.descs, (int)b->h.size(), b->ntiles,
+    Resolved rp = b->rp;
+    rp.timing = 0;  // timing events bracket the graph launch, not nodes inside it
+    int rc = enqueue(b->buf, b->v, rp, b->h[0], b->buf.descs, (int)b->h.size(), b->ntiles,
                      b->graph_stream, &nl);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->graph_stream, &g);
     if (rc) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -622,7 +710,17 @@ int iwpp_batch_launch(iwpp_batch* b, iwpp_stream_t stream, int use_graph) {
     HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     b->launches = nl;
   }
+  b->buf.timed = false;
+  if (b->rp.timing) {
+    if (!b->buf.ev[0]) HIP_TRY(hipEventCreate(&b->buf.ev[0]));
+    if (!b->buf.ev[1]) HIP_TRY(hipEventCreate(&b->buf.ev[1]));
+    HIP_TRY(hipEventRecord(b->buf.ev[0], st));
+  }
   HIP_TRY(hipGraphLaunch(b->exec, st));
+  if (b->rp.timing) {
+    HIP_TRY(hipEventRecord(b->buf.ev[1], st));
+    b->buf.timed = true;
+  }
   b->launch_rc = IWPP_OK;
   return IWPP_OK;
 }
@@ -634,15 +732,16 @@ int iwpp_batch_status(iwpp_batch* b, iwpp_stats* stats) {
   const DevCtl c = *b->buf.host_ctl;
   const int status = status_of(c, b->flags, false);
   fill_stats(c, status, (int)b->h.size(), b->ntiles, b->launches, stats);
+  if (stats) stats->kernel_ms = kernel_ms(b->buf);
   return status;
 }
 
 int iwpp_batch_destroy(iwpp_batch* b) {
   if (!b) return IWPP_E_ARG;
   (void)hipDeviceSynchronize();
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->graph_stream) hipStreamDestroy(b->graph_stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->graph_stream) (void)hipStreamDestroy(b->graph_stream);
   b->buf.release();
   delete b;
   return IWPP_OK;

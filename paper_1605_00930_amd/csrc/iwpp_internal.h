@@ -17,20 +17,33 @@ struct DevImage {
   int64_t tile_base;
 };
 
-// Control block of one launch (device memory, zeroed by the init kernel).
+// Control block of one launch (device memory, reset by the init kernel).
+// Words that many wavefronts hit with atomics sit on their own 128-byte
+// lines.
+constexpr int kMaxQueues = 8;  // one tile queue per XCD
+struct alignas(128) HotWord {
+  uint32_t v;
+  uint32_t pad[31];
+};
 struct DevCtl {
-  uint32_t q_head;   // next queue slot to claim
-  uint32_t q_tail;   // next queue slot to fill
-  int32_t pending;   // tiles queued or running
-  int32_t status;    // ST_* bits
-  uint64_t visits;   // tile visits (first visits, re-visits, in-place reprocessing)
-  uint64_t sweeps;   // rounds of the four directional passes
-  uint64_t pushes;   // entries written to tile queues
-  uint64_t overflows;
-  uint64_t reproc;   // in-place reprocessing after a neighbour changed mid-visit
-  uint32_t q_high;   // queue high-water mark
+  HotWord head[kMaxQueues];  // next ticket of each queue
+  HotWord tail[kMaxQueues];  // next fill position of each queue
+  HotWord pending;           // tiles queued or running (int32)
+  HotWord status;            // ST_* bits (int32)
+  HotWord done;              // set once no more work can arrive
+  HotWord visits_cap;        // visit counter, only used with a visit limit
+  uint64_t visits;     // tile visits (first visits, re-visits, in-place reprocessing)
+  uint64_t sweeps;     // rounds of the four directional passes
+  uint64_t pushes;     // entries processed by tile queues
+  uint64_t overflows;  // tile-queue overflows
+  uint64_t reproc;     // in-place reprocessing after a neighbour changed mid-visit
+  uint64_t requeued;   // tiles put back on a queue after their first visit
+  uint64_t qiters;     // queue-loop iterations (identify + propagate pairs)
   int32_t active_any;  // host-driven rounds: some tile was activated
-  uint64_t launches;   // filled by the host
+  int32_t pad0;
+  // wavefront time (wall_clock64 ticks, summed over workers) spent waiting
+  // for work, loading tiles, solving tiles and storing / publishing them
+  uint64_t t_idle, t_load, t_solve, t_store;
 };
 
 enum : int32_t {
@@ -51,10 +64,13 @@ struct KParams {
   int32_t sweeps;       // max rounds of directional passes before the queue
   int64_t ntiles;
   int64_t max_visits;   // 0 = unlimited
-  uint32_t qcap;        // global queue capacity (slots)
+  uint32_t qcap;        // ring capacity of each tile queue (slots)
   uint32_t spin_limit;  // bounded waits (iterations)
   int32_t first_round;  // host-driven rounds: this is the first round
-  int32_t pad;
+  int32_t seed_queue_max;  // re-visits with at most this many halo receivers skip the scans
+  int32_t nq;           // tile queues in use (1..kMaxQueues)
+  int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
+  uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
 };
 
 // Host-side launchers (iwpp_kernels.hip).  dtype: 0 = u8, 1 = i32.
@@ -64,8 +80,7 @@ struct Variant {
 };
 bool variant_supported(const Variant& v);
 hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
-                       uint8_t* visited, uint8_t* active, uint32_t order_mul,
-                       uint32_t order_add, hipStream_t st);
+                       uint8_t* visited, uint8_t* active, hipStream_t st);
 hipError_t launch_persistent(const Variant& v, const DevImage& one, const DevImage* imgs,
                              const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
                              uint8_t* visited, int grid, hipStream_t st);
@@ -76,7 +91,7 @@ hipError_t launch_clear_round(DevCtl* ctl, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 int persistent_blocks_per_cu(const Variant& v);
 
-constexpr int kTileW = 64;     // one wavefront spans a tile row
-constexpr int kThreads = 256;  // four wavefronts per workgroup
+constexpr int kTileW = 64;    // one lane per tile column
+constexpr int kThreads = 64;  // one wavefront per workgroup, one tile per wavefront
 
 }  // namespace iwpp

@@ -12,29 +12,30 @@
 // the pixels that will receive a value, and a propagation phase in which each
 // receiver only updates itself.
 //
-// GPU mapping:
-//  * One workgroup (4 wavefronts of 64 lanes) owns one 64-wide tile at a time.
-//    The tile and a 1-pixel halo of I and J are staged in LDS with coalesced
-//    row loads (a tile row is one wavefront).
-//  * Scan phase: rounds of four directional passes (down, up, right, left).
-//    A vertical pass walks rows with one lane per column; a horizontal pass
-//    walks columns with one lane per row.  Each pass takes every pixel to
-//    min(I, max(J, the three neighbours on the side it comes from)), so one
-//    round pulls from all eight neighbours.  Each pixel has a single writer
-//    per pass; reads across band borders may see old or new values, which is
-//    harmless because values only grow and are re-checked.
+// GPU mapping (one 64-lane wavefront owns one tile 64 columns wide):
+//  * The tile and a 1-pixel halo of I and J are staged in LDS; a tile row is
+//    one wavefront-wide coalesced load.
+//  * Scan phase: rounds of four directional passes over the whole tile.  The
+//    downward / upward passes walk rows with one lane per column; the
+//    rightward / leftward passes walk columns with one lane per row.  Each
+//    step takes a pixel to min(I, max(J, the three neighbours on the side the
+//    pass comes from)); the previous line lives in registers and the diagonal
+//    neighbours arrive by DPP lane shifts, so one round pulls from all eight
+//    neighbours and carries a value across the whole tile.
 //  * Seed detection: one lane per pixel tests whether a neighbour can still
 //    raise it; receivers are compacted into an LDS queue with a wavefront
-//    ballot + mbcnt prefix and one LDS atomic per wavefront (the role of the
-//    paper's popcnt / prefix-sum / scatter insertion).
+//    ballot + mbcnt prefix (the role of the paper's popcnt / prefix-sum /
+//    scatter insertion).  The wavefront keeps the queue length in a scalar
+//    register, so no LDS counter is needed.
 //  * Queue phase (two-phase IWPP): propagate -- each receiver pulls
 //    min(I, max(J, max of its neighbours)) and writes only itself; identify --
-//    the receivers that changed find their neighbours that can be raised and
-//    append them to the other LDS queue.  No pixel atomics.  A queue overflow
-//    falls back to another scan round, which is always correct.
-//  * Cross-tile propagation: after write-back, a tile activates each
-//    neighbour tile into which one of its changed border pixels can propagate.
-//    Persistent workgroups take tile ids from a global work queue; a per-tile
+//    receivers that rose find the neighbours they can raise.  A neighbour
+//    claims its place in the next queue through a bit in an LDS bitmap, so a
+//    pixel is queued at most once per wave of the queue; winners are
+//    compacted with ballot + mbcnt.  No pixel atomics.
+//  * Cross-tile propagation: after write-back a tile activates each neighbour
+//    tile into which one of its changed border pixels can propagate.
+//    Persistent wavefronts take tile ids from a global work queue; a per-tile
 //    state word keeps every tile single-owner (a tile activated while running
 //    is re-run in place by its owner after reloading its halo).  The launch
 //    ends when no tile is queued or running.
@@ -46,25 +47,35 @@
 
 namespace iwpp {
 
-constexpr int NT = kThreads;
-constexpr int NW = NT / 64;
-constexpr int TW = kTileW;
+constexpr int TW = kTileW;  // 64: one lane per tile column
+static_assert(kThreads == 64, "one wavefront per tile");
 
-// ------------------------------------------------------------ atomics
+// ------------------------------------------------------------ primitives
 
-__device__ __forceinline__ uint32_t ld_acq_u32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t ld_rlx_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int32_t ld_rlx_i32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup-wide OR.  The leading barrier orders all earlier LDS and global
-// accesses of the workgroup before the reduction's own synchronisation.
-__device__ __forceinline__ int block_any(bool p) {
-  __syncthreads();
-  return __syncthreads_or(p);
+// Lane i receives v from lane i-1; lane 0 receives `fill`.
+__device__ __forceinline__ int from_left(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
+// Lane i receives v from lane i+1; lane 63 receives `fill`.
+__device__ __forceinline__ int from_right(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+}
+
+// Orders this wavefront's LDS accesses before and after the call (a
+// one-wavefront workgroup barrier; the compiler keeps its memory fences).
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint64_t now() { return wall_clock64(); }
 
 // ------------------------------------------------------------ pixel types
 
@@ -87,9 +98,10 @@ struct Geo {
   static constexpr int P = sizeof(T) == 1 ? TW + 4 : TW + 3;
   static constexpr int ROWS = TH + 2;
   static constexpr int NPIX = TH * TW;
-  static constexpr int QCAP = TH * TW;
-  static constexpr int RING = 2 * TW + 2 * TH;            // interior border positions
-  static constexpr int HALO = 2 * (TW + 2) + 2 * TH;      // halo positions
+  static constexpr int QCAP = sizeof(T) == 1 ? NPIX : NPIX / 2;
+  static constexpr int NWORDS = NPIX / 32;
+  static constexpr int RING = 2 * TW + 2 * (TH - 2);  // border pixels, each once
+  static constexpr int HALO = 2 * (TW + 2) + 2 * TH;  // halo pixels
   __device__ static constexpr int at(int y, int x) { return (y + 1) * P + (x + 1); }
 };
 
@@ -99,111 +111,148 @@ struct Lds {
   T J[G::ROWS * G::P];
   T I[G::ROWS * G::P];
   uint16_t q[2][G::QCAP];
+  uint32_t claim[G::NWORDS];  // pixels already in the next queue
   T b_top[TW], b_bot[TW], b_left[TH], b_right[TH];  // border as loaded
   uint8_t rowdirty[TH];
-  int qn[2];
-  int act[9];
-  int viol;
-  int tile;
-  int cmd;
-  int npush;
-  int nround;
-  int novf;
 };
 
 // Queue entries are 15-bit pixel indices y * TW + x; bit 15 marks an entry
 // whose pixel rose during the propagation phase.
 constexpr uint16_t kRose = 0x8000u;
 
+// Per-visit work counters, kept by the wavefront (uniform values).
+struct VisitStats {
+  uint32_t pushes = 0, rounds = 0, iters = 0, ovf = 0;
+};
+
 template <typename T, int CONN, int TH>
 struct Tile {
   using G = Geo<T, TH>;
   using L = Lds<T, TH>;
   static constexpr int LO = Lowest<T>::v;
-  static constexpr int RG = TH / 64;  // 64-row groups (horizontal passes)
-  static constexpr int NS = NW / RG;  // column strips (horizontal passes)
-  static constexpr int SW = TW / NS;  // strip width
-  static constexpr int BAND = TH / NW;  // rows per wavefront (vertical passes)
-  static_assert(TH % 64 == 0 && NW % RG == 0 && TH / 64 <= NW, "tile height");
-  static_assert(G::NPIX <= 32768, "queue entries are 15-bit");
-  static_assert(G::NPIX % NT == 0, "whole wavefronts per scan");
+  static_assert(TH % 32 == 0 && G::NPIX <= 32768, "queue entries are 15-bit");
 
+  __device__ static int lane() { return threadIdx.x; }
   __device__ static int jv(const L& s, int y, int x) { return (int)s.J[G::at(y, x)]; }
   __device__ static int iv(const L& s, int y, int x) { return (int)s.I[G::at(y, x)]; }
 
-  // ---------------------------------------------------------- compaction
-  // Append `val` for every lane with `pred` to queue `which`.  All 64 lanes
-  // of the wavefront must call it together.
-  __device__ static void push(L& s, int which, bool pred, int val) {
+  // Append `val` for every lane with `pred` to queue `which`, whose length is
+  // the wave-uniform `n`.  Entries past the capacity are dropped; the caller
+  // sees n > QCAP.
+  __device__ static void push(L& s, int which, int& n, bool pred, int val) {
     const unsigned long long b = __ballot(pred);
-    if (b == 0) return;
-    const int n = __popcll(b);
-    int base = 0;
-    if ((threadIdx.x & 63) == 0) base = atomicAdd(&s.qn[which], n);
-    base = __builtin_amdgcn_readfirstlane(base);
     const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
                                               __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-    if (pred && base + off < G::QCAP) s.q[which][base + off] = (uint16_t)val;
+    if (pred && n + off < G::QCAP) s.q[which][n + off] = (uint16_t)val;
+    n += __popcll(b);
   }
 
   // ---------------------------------------------------------- load / store
-  // Stage tile (ty, tx) and its halo.  Pixels outside the image become the
-  // lowest value in both I and J: they can neither give nor take a value.
-  // J is clamped to I on load; a first visit reports interior J > I.
-  __device__ static void load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first) {
+  // Stage the tile at (y0, x0) and its halo.  Pixels outside the image
+  // become the lowest value in both I and J: they can neither give nor take
+  // a value.  J is clamped to I on load (a clamped pixel's row is marked
+  // dirty so that the clamp reaches memory); returns true if a first visit
+  // saw J > I inside the tile.
+  __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first) {
     const T* __restrict__ gJ = (const T*)im.J;
     const T* __restrict__ gI = (const T*)im.I;
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    wsync();
     bool viol = false;
-    constexpr int RW = TW + 2;
-    if (threadIdx.x < TH) s.rowdirty[threadIdx.x] = 0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < G::ROWS * RW; e += NT) {
-      const int yy = e / RW, xx = e - yy * RW;  // padded coordinates
-      const int64_t gy = y0 + yy - 1, gx = x0 + xx - 1;
-      int j = LO, i = LO;
-      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-        const int64_t o = gy * im.ld + gx;
-        j = (int)gJ[o];
-        i = (int)gI[o];
-        if (j > i) {
-          if (yy >= 1 && yy <= TH && xx >= 1 && xx <= TW) {
-            viol = viol || first;
-            s.rowdirty[yy - 1] = 1;  // the clamped value must reach memory
+    // Main part: lanes 0..63 cover padded columns 0..63, i.e. the left halo
+    // column and tile columns 0..62, one row per step, B rows in flight.
+    {
+      const int64_t gx = x0 + lane() - 1;
+      const bool c_in = gx >= 0 && gx < im.W;
+      constexpr int B = 16;
+      for (int yb = 0; yb < G::ROWS; yb += B) {
+        int j[B], i[B];
+        const int64_t gy0 = y0 + yb - 1;
+        const T* pj = gJ + gy0 * im.ld + gx;
+        const T* pi = gI + gy0 * im.ld + gx;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const int64_t gy = gy0 + k;
+          j[k] = i[k] = LO;
+          if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
+            j[k] = (int)pj[k * im.ld];
+            i[k] = (int)pi[k * im.ld];
           }
-          j = i;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const int yy = yb + k;
+          if (yy >= G::ROWS) continue;
+          int a = j[k];
+          const int b = i[k];
+          if (a > b) {
+            if (yy >= 1 && yy <= TH && lane() >= 1) {
+              viol = viol || first;
+              s.rowdirty[yy - 1] = 1;  // the clamped value must reach memory
+            }
+            a = b;
+          }
+          s.J[yy * G::P + lane()] = (T)a;
+          s.I[yy * G::P + lane()] = (T)b;
         }
       }
-      s.J[yy * G::P + xx] = (T)j;
-      s.I[yy * G::P + xx] = (T)i;
     }
-    if (threadIdx.x < 9) s.act[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-      s.npush = 0;
-      s.nround = 0;
-      s.novf = 0;
+    // Padded columns 64 and 65 (tile column 63 and the right halo column) of
+    // every padded row: 2 * ROWS elements spread over the lanes.
+    {
+      constexpr int NE = 2 * G::ROWS;
+      constexpr int K = (NE + 63) / 64;
+      int j[K], i[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int e = lane() + 64 * k;
+        const int yy = e >> 1, c = 64 + (e & 1);
+        const int64_t gy = y0 + yy - 1, gx = x0 + c - 1;
+        j[k] = i[k] = LO;
+        if (e < NE && gy >= 0 && gy < im.H && gx < im.W) {
+          j[k] = (int)gJ[gy * im.ld + gx];
+          i[k] = (int)gI[gy * im.ld + gx];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int e = lane() + 64 * k;
+        if (e >= NE) continue;
+        const int yy = e >> 1, c = 64 + (e & 1);
+        int a = j[k];
+        const int b = i[k];
+        if (a > b) {
+          if (yy >= 1 && yy <= TH && c == 64) {
+            viol = viol || first;
+            s.rowdirty[yy - 1] = 1;
+          }
+          a = b;
+        }
+        s.J[yy * G::P + c] = (T)a;
+        s.I[yy * G::P + c] = (T)b;
+      }
     }
-    const int any = block_any(viol);
-    if (any && threadIdx.x == 0) s.viol = 1;
+    wsync();
     snapshot_border(s);
-    __syncthreads();
+    wsync();
+    return __ballot(viol) != 0;
   }
 
   __device__ static void snapshot_border(L& s) {
-    for (int e = threadIdx.x; e < TW; e += NT) {
-      s.b_top[e] = s.J[G::at(0, e)];
-      s.b_bot[e] = s.J[G::at(TH - 1, e)];
-    }
-    for (int e = threadIdx.x; e < TH; e += NT) {
-      s.b_left[e] = s.J[G::at(e, 0)];
-      s.b_right[e] = s.J[G::at(e, TW - 1)];
+    s.b_top[lane()] = s.J[G::at(0, lane())];
+    s.b_bot[lane()] = s.J[G::at(TH - 1, lane())];
+    for (int y = lane(); y < TH; y += 64) {
+      s.b_left[y] = s.J[G::at(y, 0)];
+      s.b_right[y] = s.J[G::at(y, TW - 1)];
     }
   }
 
-  // Re-read the halo of J (the tile's own pixels in LDS are current because
-  // this workgroup is their only writer).
+  // Re-read the halo of J; the tile's own pixels in LDS are current because
+  // this wavefront is their only writer.
   __device__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0) {
     const T* __restrict__ gJ = (const T*)im.J;
-    for (int e = threadIdx.x; e < G::HALO; e += NT) {
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    for (int e = lane(); e < G::HALO; e += 64) {
       int y, x;
       if (e < TW + 2) {
         y = -1;
@@ -222,202 +271,147 @@ struct Tile {
       if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
         const int i = iv(s, y, x);
         const int j = (int)gJ[gy * im.ld + gx];
-        s.J[G::at(y, x)] = (T)(j < i ? j : i);
+        s.J[G::at(y, x)] = (T)imin(j, i);
       }
     }
-    if (threadIdx.x < TH) s.rowdirty[threadIdx.x] = 0;
-    if (threadIdx.x < 9) s.act[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-      s.npush = 0;
-      s.nround = 0;
-      s.novf = 0;
-    }
+    wsync();
     snapshot_border(s);
-    __syncthreads();
+    wsync();
   }
 
   __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0) {
     T* __restrict__ gJ = (T*)im.J;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int y = wave; y < TH; y += NW) {
-      if (!s.rowdirty[y]) continue;
-      const int64_t gy = y0 + y, gx = x0 + lane;
-      if (gy < im.H && gx < im.W) gJ[gy * im.ld + gx] = s.J[G::at(y, lane)];
+    const int64_t gx = x0 + lane();
+    const bool col_in = gx < im.W;
+    for (int g = 0; g < TH; g += 64) {
+      // lane k reports row g + k; the set bits are the rows to write back
+      unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
+      while (rows) {
+        const int y = g + __builtin_ctzll(rows);
+        rows &= rows - 1;
+        const int64_t gy = y0 + y;
+        if (gy < im.H && col_in) gJ[gy * im.ld + gx] = s.J[G::at(y, lane())];
+      }
     }
   }
 
   // ---------------------------------------------------------- scans
-  // Vertical pass, downward (D = +1) or upward (D = -1).  Wavefront w owns
-  // rows [w*BAND, (w+1)*BAND); lane = column.
+  // Downward (D = +1) or upward (D = -1) pass; lane = column.
   template <int D>
   __device__ static bool pass_vert(L& s) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x = lane;
-    const int ybeg = D > 0 ? wave * BAND : wave * BAND + BAND - 1;
-    const int yprev = ybeg - D;
-    int pc = jv(s, yprev, x);
+    const int x = lane();
+    const int y0 = D > 0 ? 0 : TH - 1;
+    int pc = jv(s, y0 - D, x);
     int pl = LO, pr = LO;
     if (CONN == 8) {
-      pl = jv(s, yprev, x - 1);
-      pr = jv(s, yprev, x + 1);
+      pl = jv(s, y0 - D, x - 1);
+      pr = jv(s, y0 - D, x + 1);
     }
     bool any = false;
-#pragma unroll 2
-    for (int k = 0; k < BAND; ++k) {
-      const int y = ybeg + D * k;
+#pragma unroll 4
+    for (int k = 0; k < TH; ++k) {
+      const int y = y0 + D * k;
       const int a = G::at(y, x);
       const int j = (int)s.J[a], i = (int)s.I[a];
-      int m = j > pc ? j : pc;
-      if (CONN == 8) {
-        const int d = pl > pr ? pl : pr;
-        m = m > d ? m : d;
-      }
-      const int v = m < i ? m : i;
+      int m = imax(j, pc);
+      if (CONN == 8) m = imax(m, imax(pl, pr));
+      const int v = imin(m, i);
       const bool c = v != j;
       if (c) s.J[a] = (T)v;
       if (__ballot(c)) {
-        if (lane == 0) s.rowdirty[y] = 1;
+        if (x == 0) s.rowdirty[y] = 1;
         any = true;
       }
       pc = v;
       if (CONN == 8) {
-        pl = __shfl_up(v, 1);
-        pr = __shfl_down(v, 1);
-        if (x == 0) pl = jv(s, y, -1);
-        if (x == TW - 1) pr = jv(s, y, TW);
+        pl = from_left(v, jv(s, y, -1));
+        pr = from_right(v, jv(s, y, TW));
       }
     }
     return any;
   }
 
-  // Horizontal pass, rightward (D = +1) or leftward (D = -1).  Wavefront w
-  // owns a strip of SW columns of one 64-row group; lane = row.
+  // Rightward (D = +1) or leftward (D = -1) pass; lane = row of a 64-row
+  // group, groups taken top to bottom.
   template <int D>
   __device__ static bool pass_horz(L& s) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rg = wave % RG, strip = wave / RG;
-    const int y = rg * 64 + lane;
-    const int xbeg = D > 0 ? strip * SW : strip * SW + SW - 1;
-    const int xprev = xbeg - D;
-    int pc = jv(s, y, xprev);
-    int pu = LO, pd = LO;
-    if (CONN == 8) {
-      pu = jv(s, y - 1, xprev);
-      pd = jv(s, y + 1, xprev);
-    }
-    bool dirty = false;
-#pragma unroll 2
-    for (int k = 0; k < SW; ++k) {
-      const int x = xbeg + D * k;
-      const int a = G::at(y, x);
-      const int j = (int)s.J[a], i = (int)s.I[a];
-      int m = j > pc ? j : pc;
+    bool any = false;
+    for (int g = 0; g < TH; g += 64) {
+      const int nrows = TH - g < 64 ? TH - g : 64;  // 32-row tiles use half the lanes
+      const int y = g + lane();
+      const bool live = lane() < nrows;
+      const int yc = live ? y : g;  // dead lanes shadow row g
+      const int x0 = D > 0 ? 0 : TW - 1;
+      int pc = jv(s, yc, x0 - D);
+      int pu = LO, pd = LO;
       if (CONN == 8) {
-        const int d = pu > pd ? pu : pd;
-        m = m > d ? m : d;
+        pu = jv(s, yc - 1, x0 - D);
+        pd = jv(s, yc + 1, x0 - D);
       }
-      const int v = m < i ? m : i;
-      if (v != j) {
-        s.J[a] = (T)v;
-        dirty = true;
+      bool dirty = false;
+#pragma unroll 4
+      for (int k = 0; k < TW; ++k) {
+        const int x = x0 + D * k;
+        const int a = G::at(yc, x);
+        const int j = (int)s.J[a], i = (int)s.I[a];
+        int m = imax(j, pc);
+        if (CONN == 8) m = imax(m, imax(pu, pd));
+        const int v = imin(m, i);
+        if (live && v != j) {
+          s.J[a] = (T)v;
+          dirty = true;
+        }
+        pc = v;
+        if (CONN == 8) {
+          // row y-1 of this group comes from lane y-1; the group's edges read
+          // the neighbouring row from LDS (halo or another group)
+          pu = from_left(v, jv(s, g - 1, x));
+          pd = from_right(v, jv(s, g + nrows, x));
+          if (nrows < 64 && lane() == nrows - 1) pd = jv(s, g + nrows, x);
+        }
       }
-      pc = v;
-      if (CONN == 8) {
-        pu = __shfl_up(v, 1);
-        pd = __shfl_down(v, 1);
-        if (lane == 0) pu = jv(s, y - 1, x);
-        if (lane == 63) pd = jv(s, y + 1, x);
-      }
+      if (dirty) s.rowdirty[y] = 1;
+      any = __ballot(dirty) != 0 || any;
+      wsync();
     }
-    if (dirty) s.rowdirty[y] = 1;
-    return __ballot(dirty) != 0;
+    return any;
   }
 
   // One round of the four passes; true if any pixel of the tile rose.
-  __device__ static bool sweep_round(L& s) {
+  __device__ static bool sweep_round(L& s, VisitStats& vs) {
     bool c = pass_vert<+1>(s);
-    __syncthreads();
-    c |= pass_vert<-1>(s);
-    __syncthreads();
-    c |= pass_horz<+1>(s);
-    __syncthreads();
-    c |= pass_horz<-1>(s);
-    if (threadIdx.x == 0) s.nround++;
-    return block_any(c) != 0;
+    wsync();
+    c = pass_vert<-1>(s) || c;
+    wsync();
+    c = pass_horz<+1>(s) || c;
+    c = pass_horz<-1>(s) || c;
+    vs.rounds++;
+    return c;
   }
 
   // ---------------------------------------------------------- seeds
-  // Largest J over the neighbourhood of interior pixel (y, x), halo included.
   __device__ static int nbr_max(const L& s, int y, int x) {
     const int a = G::at(y, x);
     constexpr int P = G::P;
-    int m = (int)s.J[a - P];
-    int t = (int)s.J[a + P];
-    m = m > t ? m : t;
-    t = (int)s.J[a - 1];
-    m = m > t ? m : t;
-    t = (int)s.J[a + 1];
-    m = m > t ? m : t;
-    if (CONN == 8) {
-      t = (int)s.J[a - P - 1];
-      m = m > t ? m : t;
-      t = (int)s.J[a - P + 1];
-      m = m > t ? m : t;
-      t = (int)s.J[a + P - 1];
-      m = m > t ? m : t;
-      t = (int)s.J[a + P + 1];
-      m = m > t ? m : t;
-    }
+    int m = imax(imax((int)s.J[a - P], (int)s.J[a + P]), imax((int)s.J[a - 1], (int)s.J[a + 1]));
+    if (CONN == 8)
+      m = imax(m, imax(imax((int)s.J[a - P - 1], (int)s.J[a - P + 1]),
+                       imax((int)s.J[a + P - 1], (int)s.J[a + P + 1])));
     return m;
   }
 
-  // Every pixel some neighbour can still raise goes to queue 0.
-  __device__ static void scan_receivers(L& s) {
-    if (threadIdx.x == 0) s.qn[0] = 0;
-    __syncthreads();
+  // Every pixel a neighbour can still raise goes to queue 0; returns its length.
+  __device__ static int scan_receivers(L& s) {
+    int n = 0;
 #pragma unroll 1
-    for (int base = 0; base < G::NPIX; base += NT) {
-      const int idx = base + threadIdx.x;
-      const int y = idx / TW, x = idx % TW;
-      const int a = G::at(y, x);
+    for (int y = 0; y < TH; ++y) {
+      const int a = G::at(y, lane());
       const int j = (int)s.J[a], i = (int)s.I[a];
-      bool r = false;
-      if (j < i) r = nbr_max(s, y, x) > j;
-      push(s, 0, r, idx);
+      const bool r = j < i && nbr_max(s, y, lane()) > j;
+      push(s, 0, n, r, y * TW + lane());
     }
-    __syncthreads();
-  }
-
-  // Border pixels that a (new) halo value can raise go to queue 0.
-  __device__ static void halo_receivers(L& s) {
-    if (threadIdx.x == 0) s.qn[0] = 0;
-    __syncthreads();
-    for (int base = 0; base < G::RING; base += NT) {
-      const int e = base + threadIdx.x;
-      bool r = false;
-      int idx = 0;
-      if (e < G::RING) {
-        int y, x;
-        ring_pos(e, y, x);
-        idx = y * TW + x;
-        const int j = jv(s, y, x), i = iv(s, y, x);
-        if (j < i) {
-          for (int dy = -1; dy <= 1 && !r; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              if (dy == 0 && dx == 0) continue;
-              if (CONN == 4 && dy != 0 && dx != 0) continue;
-              const int hy = y + dy, hx = x + dx;
-              if (hy >= 0 && hy < TH && hx >= 0 && hx < TW) continue;
-              if (jv(s, hy, hx) > j) {
-                r = true;
-                break;
-              }
-            }
-        }
-      }
-      push(s, 0, r, idx);
-    }
-    __syncthreads();
+    wsync();
+    return n;
   }
 
   __device__ static void ring_pos(int e, int& y, int& x) {
@@ -427,26 +421,54 @@ struct Tile {
     } else if (e < 2 * TW) {
       y = TH - 1;
       x = e - TW;
-    } else if (e < 2 * TW + TH) {
-      y = e - 2 * TW;
+    } else if (e < 2 * TW + TH - 2) {
+      y = e - 2 * TW + 1;
       x = 0;
     } else {
-      y = e - 2 * TW - TH;
+      y = e - 2 * TW - (TH - 2) + 1;
       x = TW - 1;
     }
   }
 
+  // Border pixels a halo value can raise go to queue 0; returns its length.
+  __device__ static int halo_receivers(L& s) {
+    int n = 0;
+    for (int base = 0; base < G::RING; base += 64) {
+      const int e = base + lane();
+      bool r = false;
+      int idx = 0;
+      if (e < G::RING) {
+        int y, x;
+        ring_pos(e, y, x);
+        idx = y * TW + x;
+        const int j = jv(s, y, x), i = iv(s, y, x);
+        if (j < i) {
+          for (int d = 0; d < 9; ++d) {
+            const int dy = d / 3 - 1, dx = d % 3 - 1;
+            if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
+            const int hy = y + dy, hx = x + dx;
+            if (hy >= 0 && hy < TH && hx >= 0 && hx < TW) continue;
+            r = r || jv(s, hy, hx) > j;
+          }
+        }
+      }
+      push(s, 0, n, r, idx);
+    }
+    wsync();
+    return n;
+  }
+
   // ---------------------------------------------------------- queue phase
-  // Two-phase queue loop on queue 0 (receivers).  Returns false when the
-  // queue ran dry (the tile is at a fixed point), true on overflow.
-  __device__ static bool queue_loop(L& s, uint32_t iter_limit, bool& hit_limit) {
-    int cur = 0;
+  // Two-phase queue loop starting from n receivers in queue 0.  Returns
+  // false when the queue ran dry (the tile is at a fixed point), true on
+  // overflow (then a scan round must follow).
+  __device__ static bool queue_loop(L& s, int n, VisitStats& vs, uint32_t iter_limit,
+                                    bool& hit_limit) {
+    for (int w = lane(); w < G::NWORDS; w += 64) s.claim[w] = 0;
+    wsync();
     for (uint32_t iter = 0;; ++iter) {
-      const int n = s.qn[cur];
-      const int nxt = cur ^ 1;
       if (n > G::QCAP) {
-        if (threadIdx.x == 0) s.novf++;
-        __syncthreads();
+        vs.ovf++;
         return true;
       }
       if (n == 0) return false;
@@ -454,31 +476,32 @@ struct Tile {
         hit_limit = true;
         return false;
       }
-      if (threadIdx.x == 0) s.npush += n;
+      vs.iters++;
+      vs.pushes += n;
       // propagation: each receiver updates only itself
-      for (int e = threadIdx.x; e < n; e += NT) {
-        const int idx = s.q[cur][e];
+      for (int e = lane(); e < n; e += 64) {
+        const int idx = s.q[0][e];
         const int y = idx / TW, x = idx % TW;
         const int a = G::at(y, x);
-        const int j = (int)s.J[a], i = (int)s.I[a];
-        int v = nbr_max(s, y, x);
-        v = v < i ? v : i;
+        const int j = (int)s.J[a];
+        const int v = imin(nbr_max(s, y, x), (int)s.I[a]);
         if (v > j) {
           s.J[a] = (T)v;
           s.rowdirty[y] = 1;
-          s.q[cur][e] = (uint16_t)(idx | kRose);
+          s.q[0][e] = (uint16_t)(idx | kRose);
         }
       }
-      if (threadIdx.x == 0) s.qn[nxt] = 0;
-      __syncthreads();
-      // identification: neighbours of risen pixels that can now be raised
+      wsync();
+      // identification: neighbours of risen pixels that can now be raised,
+      // each claimed once through the bitmap
+      int nn = 0;
 #pragma unroll 1
-      for (int base = 0; base < n; base += NT) {
-        const int e = base + threadIdx.x;
+      for (int base = 0; base < n; base += 64) {
+        const int e = base + lane();
         int idx = 0, jp = LO;
         bool live = false;
         if (e < n) {
-          const int q = s.q[cur][e];
+          const int q = s.q[0][e];
           if (q & kRose) {
             live = true;
             idx = q & ~kRose;
@@ -489,45 +512,55 @@ struct Tile {
 #pragma unroll
         for (int d = 0; d < 9; ++d) {
           const int dy = d / 3 - 1, dx = d % 3 - 1;
-          if (d == 4) continue;
-          if (CONN == 4 && dy != 0 && dx != 0) continue;
+          if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
           const int yy = y + dy, xx = x + dx;
-          bool r = false;
+          bool win = false;
+          const int qi = yy * TW + xx;
           if (live && yy >= 0 && yy < TH && xx >= 0 && xx < TW) {
             const int a = G::at(yy, xx);
             const int jq = (int)s.J[a];
-            r = jq < jp && jq < (int)s.I[a];
+            if (jq < jp && jq < (int)s.I[a]) {
+              const uint32_t bit = 1u << (qi & 31);
+              win = !(atomicOr(&s.claim[qi >> 5], bit) & bit);
+            }
           }
-          push(s, nxt, r, yy * TW + xx);
+          push(s, 1, nn, win, qi);
         }
       }
-      __syncthreads();
-      cur = nxt;
+      wsync();
+      n = nn;
+      for (int w = lane(); w < G::NWORDS; w += 64) s.claim[w] = 0;
+      if (n <= G::QCAP)
+        for (int e = lane(); e < n; e += 64) s.q[0][e] = s.q[1][e];
+      wsync();
     }
   }
 
-  // ---------------------------------------------------------- full visit
-  // Bring the tile to a fixed point given its (fixed) halo.
-  __device__ static void solve(L& s, int sweeps, bool seeded, uint32_t iter_limit,
-                               bool& hit_limit) {
+  // ---------------------------------------------------------- visit
+  // Bring the tile to a fixed point given its (fixed) halo.  `seeded`: the
+  // tile was at a fixed point for an older halo, so only border pixels next
+  // to a changed halo pixel can rise at first.
+  __device__ static void solve(L& s, int sweeps, bool seeded, int seed_queue_max,
+                               uint32_t iter_limit, VisitStats& vs, bool& hit_limit) {
     int budget = sweeps;
     if (seeded) {
-      // The tile was at a fixed point for its previous halo: only border
-      // pixels next to a changed halo pixel can be raised at first.
-      halo_receivers(s);
-      if (!queue_loop(s, iter_limit, hit_limit)) return;
+      const int n = halo_receivers(s);
+      if (n == 0) return;
+      if (n <= seed_queue_max) {
+        if (!queue_loop(s, n, vs, iter_limit, hit_limit)) return;
+      }
       if (budget < 1) budget = 1;
     }
     for (uint32_t guard = 0;; ++guard) {
       bool ch = true;
-      for (int r = 0; r < budget; ++r) {
-        ch = sweep_round(s);
-        if (!ch) break;
+      for (int r = 0; r < budget && ch; ++r) {
+        ch = sweep_round(s, vs);
+        wsync();
       }
       if (!ch) return;  // a round that changed nothing: fixed point
-      scan_receivers(s);
-      if (s.qn[0] == 0) return;
-      if (!queue_loop(s, iter_limit, hit_limit)) return;
+      const int n = scan_receivers(s);
+      if (n == 0) return;
+      if (!queue_loop(s, n, vs, iter_limit, hit_limit)) return;
       if (budget < 1) budget = 1;
       if (guard >= iter_limit) {
         hit_limit = true;
@@ -536,11 +569,14 @@ struct Tile {
     }
   }
 
-  // Mark the neighbour tiles (3x3 grid index) that a changed border pixel
-  // can propagate into.  Halo values are the ones seen at load time; they
-  // never exceed the current ones, so no needed activation is missed.
-  __device__ static void activation_flags(L& s) {
-    for (int e = threadIdx.x; e < G::RING; e += NT) {
+  // Neighbour tiles (3x3 grid index) that a changed border pixel can
+  // propagate into.  Halo values are the ones seen at load time; they never
+  // exceed the current ones, so no needed activation is missed.
+  __device__ static uint32_t activation_mask(const L& s) {
+    uint32_t m = 0;
+    for (int base = 0; base < G::RING; base += 64) {
+      const int e = base + lane();
+      if (e >= G::RING) continue;
       int y, x;
       ring_pos(e, y, x);
       const int j = jv(s, y, x);
@@ -549,34 +585,27 @@ struct Tile {
         j0 = (int)s.b_top[x];
       else if (e < 2 * TW)
         j0 = (int)s.b_bot[x];
-      else if (e < 2 * TW + TH)
+      else if (e < 2 * TW + TH - 2)
         j0 = (int)s.b_left[y];
       else
         j0 = (int)s.b_right[y];
       if (j == j0) continue;
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          if (dy == 0 && dx == 0) continue;
-          if (CONN == 4 && dy != 0 && dx != 0) continue;
-          const int hy = y + dy, hx = x + dx;
-          const int cy = hy < 0 ? 0 : (hy >= TH ? 2 : 1);
-          const int cx = hx < 0 ? 0 : (hx >= TW ? 2 : 1);
-          if (cy == 1 && cx == 1) continue;
-          const int jh = jv(s, hy, hx);
-          if (j > jh && jh < iv(s, hy, hx)) s.act[cy * 3 + cx] = 1;
-        }
+      for (int d = 0; d < 9; ++d) {
+        const int dy = d / 3 - 1, dx = d % 3 - 1;
+        if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
+        const int hy = y + dy, hx = x + dx;
+        const int cy = hy < 0 ? 0 : (hy >= TH ? 2 : 1);
+        const int cx = hx < 0 ? 0 : (hx >= TW ? 2 : 1);
+        if (cy == 1 && cx == 1) continue;
+        const int jh = jv(s, hy, hx);
+        if (j > jh && jh < iv(s, hy, hx)) m |= 1u << (cy * 3 + cx);
+      }
     }
-  }
-
-  // Load, solve and write back tile t of image im.
-  __device__ static void visit(L& s, const DevImage& im, int64_t t_local, bool first,
-                               int sweeps, uint32_t iter_limit, bool& hit_limit) {
-    const int64_t ty = t_local / im.tiles_x, tx = t_local % im.tiles_x;
-    const int64_t y0 = ty * TH, x0 = tx * TW;
-    load(s, im, y0, x0, first);
-    solve(s, sweeps, !first, iter_limit, hit_limit);
-    store(s, im, y0, x0);
-    activation_flags(s);
+    // OR across the wavefront
+    uint32_t all = 0;
+    for (int d = 0; d < 9; ++d)
+      if (__ballot((m >> d) & 1u)) all |= 1u << d;
+    return all;
   }
 };
 
@@ -594,145 +623,263 @@ __device__ __forceinline__ int find_image(const DevImage* imgs, int nimg, int64_
   return lo;
 }
 
-__device__ __forceinline__ void flush_stats(DevCtl* ctl, int npush, int nround, int novf) {
-  if (npush) atomicAdd((unsigned long long*)&ctl->pushes, (unsigned long long)npush);
-  if (nround) atomicAdd((unsigned long long*)&ctl->sweeps, (unsigned long long)nround);
-  if (novf) atomicAdd((unsigned long long*)&ctl->overflows, (unsigned long long)novf);
+__device__ __forceinline__ void add64(uint64_t* p, uint64_t v) {
+  if (v) atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
+
+// Per-worker totals, flushed once when the worker exits.
+struct WorkerStats {
+  uint64_t pushes = 0, rounds = 0, iters = 0, ovf = 0, visits = 0, reproc = 0, requeued = 0;
+  uint64_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0;
+  __device__ void add(const VisitStats& v) {
+    pushes += v.pushes;
+    rounds += v.rounds;
+    iters += v.iters;
+    ovf += v.ovf;
+  }
+  __device__ void flush(DevCtl* ctl) const {
+    add64(&ctl->pushes, pushes);
+    add64(&ctl->sweeps, rounds);
+    add64(&ctl->qiters, iters);
+    add64(&ctl->overflows, ovf);
+    add64(&ctl->visits, visits);
+    add64(&ctl->reproc, reproc);
+    add64(&ctl->requeued, requeued);
+    add64(&ctl->t_idle, t_idle);
+    add64(&ctl->t_load, t_load);
+    add64(&ctl->t_solve, t_solve);
+    add64(&ctl->t_store, t_store);
+  }
+};
 
 // ------------------------------------------------------------ persistent
+//
+// Tile queues.  Tile t belongs to queue (t / chunk) % nq; workgroup w
+// serves queue w % nq (workgroups are dealt to the 8 XCDs in turn, so a
+// queue's tiles are handled under one L2, and chunks of neighbouring tiles
+// are spread over all queues).  A pop is one atomicAdd on the queue head:
+// ticket h.  Tickets below the queue's first-pass length map directly to
+// the tiles of the initial pass (no ring traffic); later tickets wait on
+// their ring slot until a producer fills it.  The worker that brings the
+// pending count to zero marks the launch done and writes a stop value into
+// every slot a waiter may hold.
 
-// Enqueue tile n (caller has just moved it from idle to pending).
-__device__ void queue_push(DevCtl* ctl, int* queue, uint32_t qcap, int n) {
-  const uint32_t slot = atomicAdd(&ctl->q_tail, 1u);
-  __hip_atomic_store(&queue[slot % qcap], n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t head = ld_acq_u32(&ctl->q_head);
-  const uint32_t depth = slot + 1 - head;
-  if ((int32_t)depth > 0) atomicMax(&ctl->q_high, depth);
+constexpr int kSlotEmpty = -1;
+constexpr int kSlotStop = -3;
+
+__device__ __forceinline__ int queue_of(const KParams& kp, int64_t t) {
+  return (int)((t / kp.chunk) % kp.nq);
 }
 
-// Take a tile id, or -1 when the launch is over (or aborted).
-__device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state) {
-  for (uint32_t spin = 0;; ++spin) {
-    if (ld_rlx_i32(&ctl->status) & ST_ABORT) return -1;
-    const uint32_t h = ld_acq_u32(&ctl->q_head);
-    const uint32_t tl = ld_acq_u32(&ctl->q_tail);
-    if ((int32_t)(tl - h) > 0) {
-      uint32_t expect = h;
-      if (!__hip_atomic_compare_exchange_strong(&ctl->q_head, &expect, h + 1u, __ATOMIC_ACQ_REL,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        continue;
-      int* slot = &queue[h % kp.qcap];
-      int v = -1;
-      for (uint32_t w = 0;; ++w) {
-        v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (v >= 0) break;
-        if (w > kp.spin_limit) {
-          atomicOr(&ctl->status, ST_INTERNAL | ST_ABORT);
-          return -1;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      __hip_atomic_store(slot, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned long long nv = atomicAdd((unsigned long long*)&ctl->visits, 1ull);
-      if (kp.max_visits > 0 && (long long)nv >= kp.max_visits) {
-        atomicOr(&ctl->status, ST_INCOMPLETE | ST_ABORT);
+// Number of tiles of queue q's first pass: chunks q, q + nq, ...
+__device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
+  const int64_t nchunks = (kp.ntiles + kp.chunk - 1) / kp.chunk;
+  if (q >= nchunks) return 0;
+  const int64_t nc = (nchunks - 1 - q) / kp.nq + 1;
+  int64_t len = nc * kp.chunk;
+  if (q + (nc - 1) * kp.nq == nchunks - 1) len -= nchunks * kp.chunk - kp.ntiles;
+  return len;
+}
+
+__device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, int q, int64_t i) {
+  const int64_t c = (i / kp.chunk) * kp.nq + q;
+  const int64_t t = c * kp.chunk + i % kp.chunk;
+  if (kp.order_mul == 1 && kp.order_add == 0) return t;
+  return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);
+}
+
+__device__ __forceinline__ int* ring_slot(int* queue, const KParams& kp, int q, int64_t pos,
+                                          int64_t len) {
+  return &queue[(int64_t)q * kp.qcap + (pos - len) % (int64_t)kp.qcap];
+}
+
+// Enqueue tile n (the caller has just moved it from idle to pending).
+__device__ void queue_push(DevCtl* ctl, int* queue, const KParams& kp, int n) {
+  const int q = queue_of(kp, n);
+  const uint32_t pos = atomicAdd(&ctl->tail[q].v, 1u);
+  __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// No more work: tell every waiter.  Executed by a whole wavefront.
+__device__ void stop_all(DevCtl* ctl, int* queue, const KParams& kp, int grid) {
+  __hip_atomic_store(&ctl->done.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q = 0; q < kp.nq; ++q) {
+    const int64_t len = first_pass_len(kp, q);
+    const int64_t h = ld_rlx_u32(&ctl->head[q].v);
+    int64_t t = ld_rlx_u32(&ctl->tail[q].v);
+    if (t < len) t = len;
+    // waiters hold tickets in [tail, head); a worker that passed the `done`
+    // check but has not taken its ticket yet lands within `grid` more
+    const int64_t hi = (h > t ? h : t) + grid;
+    for (int64_t pos = t + threadIdx.x; pos < hi; pos += 64)
+      __hip_atomic_store(ring_slot(queue, kp, q, pos, len), kSlotStop, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, int grid, int bits) {
+  atomicOr((int*)&ctl->status.v, bits | ST_ABORT);
+  __hip_atomic_store(&ctl->done.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q = 0; q < kp.nq; ++q) {  // one lane: this path only ends a failed launch
+    const int64_t len = first_pass_len(kp, q);
+    const int64_t h = ld_rlx_u32(&ctl->head[q].v);
+    int64_t t = ld_rlx_u32(&ctl->tail[q].v);
+    if (t < len) t = len;
+    const int64_t hi = (h > t ? h : t) + grid;
+    for (int64_t pos = t; pos < hi; ++pos)
+      __hip_atomic_store(ring_slot(queue, kp, q, pos, len), kSlotStop, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Take a tile id from queue q, or -1 when the launch is over.  Waits use
+// relaxed loads only: an acquire on gfx950 invalidates the L2 of the XCD,
+// which a waiting worker must not do to the tiles others are working on.
+// The one acquire is the exchange on the tile's state word.
+__device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
+                         int grid) {
+  if (ld_rlx_u32(&ctl->done.v)) return -1;
+  const uint32_t h = atomicAdd(&ctl->head[q].v, 1u);
+  const int64_t len = first_pass_len(kp, q);
+  int v;
+  if ((int64_t)h < len) {
+    v = (int)first_pass_tile(kp, q, h);
+  } else {
+    int* slot = ring_slot(queue, kp, q, h, len);
+    uint32_t nap = 1;
+    for (uint32_t w = 0;; ++w) {
+      v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= 0) break;
+      if (v == kSlotStop) return -1;
+      if ((w & 63) == 63 && ld_rlx_u32(&ctl->done.v)) return -1;
+      if (w > kp.spin_limit) {
+        abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
         return -1;
       }
-      // pending -> running (acquire: the tile and its halo become visible)
-      __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      return v;
+      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(2);
+      if (nap < 16) nap <<= 1;
     }
-    if (__hip_atomic_load(&ctl->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
-      return -1;
-    if (spin > kp.spin_limit) {
-      atomicOr(&ctl->status, ST_INTERNAL | ST_ABORT);
-      return -1;
-    }
-    __builtin_amdgcn_s_sleep(2);
+    __hip_atomic_store(slot, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (kp.max_visits > 0) {
+    const uint32_t nv = atomicAdd(&ctl->visits_cap.v, 1u);
+    if ((int64_t)nv >= kp.max_visits) {
+      abort_launch(ctl, queue, kp, grid, ST_INCOMPLETE);
+      return -1;
+    }
+  }
+  // pending -> running; the acquire makes the tile and its halo visible
+  __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
 }
 
-// Ask for neighbour n to be (re)visited.
-__device__ void activate(DevCtl* ctl, int* queue, uint32_t qcap, uint32_t* state, int n) {
-  const uint32_t old =
-      __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  if (old == 0u) {  // was idle: this workgroup enqueues it
-    __hip_atomic_fetch_add(&ctl->pending, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    queue_push(ctl, queue, qcap, n);
+// Publish the end of a visit of tile t (lane 0 only; the wavefront has
+// executed an agent-scope release fence after writing the tile): ask the
+// neighbours in `act` for a visit, release t, and keep the pending count.
+// Returns 1 if t must be run again (a neighbour asked while it ran), 2 if
+// this visit completed the launch, 0 otherwise.
+__device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
+                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act,
+                       WorkerStats& ws) {
+  int fresh[8];
+  int nfresh = 0;
+  for (int d = 0; d < 9; ++d) {
+    if (!((act >> d) & 1u)) continue;
+    const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
+    if (ny < 0 || ny >= im.tiles_y || nx < 0 || nx >= im.tiles_x) continue;
+    const int n = (int)(im.tile_base + ny * im.tiles_x + nx);
+    const uint32_t old =
+        __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) fresh[nfresh++] = n;  // was idle: this wavefront enqueues it
   }
-}
-
-// Release tile t.  Returns true if a neighbour asked for it while it ran, in
-// which case the caller keeps ownership and must run it again.
-__device__ bool finish(DevCtl* ctl, uint32_t* state, int t) {
   uint32_t expect = TS_RUNNING;
-  if (__hip_atomic_compare_exchange_strong(&state[t], &expect, 0u, __ATOMIC_ACQ_REL,
-                                           __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-    __hip_atomic_fetch_add(&ctl->pending, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    return false;
+  const bool released = __hip_atomic_compare_exchange_strong(
+      &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // count the new tiles before they become visible; the running tile keeps
+  // the count above zero until this update
+  const int delta = nfresh - (released ? 1 : 0);
+  int result = 0;
+  if (delta != 0) {
+    const int old = atomicAdd((int*)&ctl->pending.v, delta);
+    if (old + delta == 0) result = 2;
   }
-  // running | pending: clear the request and run again
-  __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  atomicAdd((unsigned long long*)&ctl->reproc, 1ull);
-  atomicAdd((unsigned long long*)&ctl->visits, 1ull);
-  return true;
+  for (int k = 0; k < nfresh; ++k) queue_push(ctl, queue, kp, fresh[k]);
+  ws.requeued += nfresh;
+  if (!released) {
+    // running | pending: take the request (acquire: the neighbour's new
+    // border becomes visible) and run again
+    __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    ws.reproc++;
+    ws.visits++;
+    result = 1;
+  }
+  return result;
 }
 
 template <typename T, int CONN, int TH>
-__global__ __launch_bounds__(NT) void k_persistent(DevImage one, const DevImage* __restrict__ imgs,
+__global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage* __restrict__ imgs,
                                                    KParams kp, DevCtl* ctl, int* queue,
                                                    uint32_t* state, uint8_t* visited) {
   using TP = Tile<T, CONN, TH>;
   __shared__ typename TP::L s;
-  const uint32_t iter_limit = kp.spin_limit;
+  const bool lead = threadIdx.x == 0;
+  const int q = blockIdx.x % kp.nq;
+  const int grid = gridDim.x;
+  WorkerStats ws;
   for (;;) {
-    if (threadIdx.x == 0) {
-      s.tile = queue_pop(ctl, queue, kp, state);
-      s.viol = 0;
-    }
-    __syncthreads();
-    const int t = s.tile;
+    uint64_t c0 = now();
+    int t = 0;
+    if (lead) t = queue_pop(ctl, queue, kp, state, q, grid);
+    t = __builtin_amdgcn_readfirstlane(t);
+    uint64_t c1 = now();
+    ws.t_idle += c1 - c0;
     if (t < 0) break;
+    ws.visits++;
     const int k = imgs ? find_image(imgs, kp.nimg, t) : 0;
     const DevImage im = imgs ? imgs[k] : one;
     const int64_t tl = (int64_t)t - im.tile_base;
     const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
     const int64_t y0 = ty * TH, x0 = tx * TW;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const bool first = visited[t] == 0;
+    VisitStats vs;
     bool hit = false;
-    TP::visit(s, im, tl, first, kp.sweeps, iter_limit, hit);
+    const bool viol = TP::load(s, im, y0, x0, first);
+    uint64_t c2 = now();
+    ws.t_load += c2 - c1;
+    TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.spin_limit, vs, hit);
+    uint64_t c3 = now();
+    ws.t_solve += c3 - c2;
     for (;;) {
+      TP::store(s, im, y0, x0);
+      const uint32_t act = TP::activation_mask(s);
       // publish the tile before anyone is told about it
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const int hit_any = block_any(hit);
-      if (threadIdx.x == 0) {
+      int res = 0;
+      if (lead) {
         if (first) visited[t] = 1;
-        if (s.viol) atomicOr(&ctl->status, ST_MARKER_GT_MASK);
-        if (hit_any) atomicOr(&ctl->status, ST_INTERNAL | ST_ABORT);
-        flush_stats(ctl, s.npush, s.nround, s.novf);
-        for (int d = 0; d < 9; ++d) {
-          if (!s.act[d]) continue;
-          const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
-          if (ny < 0 || ny >= im.tiles_y || nx < 0 || nx >= im.tiles_x) continue;
-          activate(ctl, queue, kp.qcap, state, (int)(im.tile_base + ny * im.tiles_x + nx));
-        }
-        s.cmd = finish(ctl, state, t) ? 1 : 0;
-        s.viol = 0;
+        if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
+        ws.add(vs);
+        if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
+        res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
       }
-      __syncthreads();
-      if (!s.cmd) break;
-      // a neighbour changed while this tile ran: reload the halo and continue
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      TP::reload_halo(s, im, y0, x0);
+      res = __builtin_amdgcn_readfirstlane(res);
+      if (res == 2) stop_all(ctl, queue, kp, grid);
+      uint64_t c4 = now();
+      ws.t_store += c4 - c3;
+      if (res != 1) break;
+      // a neighbour changed while this tile ran: reload the halo, continue
+      vs = VisitStats();
       hit = false;
-      TP::solve(s, kp.sweeps, true, iter_limit, hit);
-      TP::store(s, im, y0, x0);
-      TP::activation_flags(s);
+      TP::reload_halo(s, im, y0, x0);
+      uint64_t c5 = now();
+      ws.t_load += c5 - c4;
+      TP::solve(s, kp.sweeps, true, kp.seed_queue_max, kp.spin_limit, vs, hit);
+      c3 = now();
+      ws.t_solve += c3 - c5;
     }
-    __syncthreads();
   }
+  if (lead) ws.flush(ctl);
 }
 
 // ------------------------------------------------------------ host-driven rounds
@@ -742,7 +889,7 @@ __global__ __launch_bounds__(NT) void k_persistent(DevImage one, const DevImage*
 // dispatcher deals workgroups to the 8 XCDs in turn) gets a contiguous run
 // of tiles, keeping neighbouring tiles under one L2.
 template <typename T, int CONN, int TH>
-__global__ __launch_bounds__(NT) void k_round(DevImage one, const DevImage* __restrict__ imgs,
+__global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __restrict__ imgs,
                                               KParams kp, DevCtl* ctl, uint8_t* act_cur,
                                               uint8_t* act_next, uint8_t* visited) {
   using TP = Tile<T, CONN, TH>;
@@ -754,19 +901,24 @@ __global__ __launch_bounds__(NT) void k_round(DevImage one, const DevImage* __re
   const DevImage im = imgs ? imgs[k] : one;
   const int64_t tl = t - im.tile_base;
   const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
+  const int64_t y0 = ty * TH, x0 = tx * TW;
   const bool first = visited[t] == 0;
-  if (threadIdx.x == 0) s.viol = 0;
+  VisitStats vs;
   bool hit = false;
-  TP::visit(s, im, tl, first, kp.sweeps, kp.spin_limit, hit);
-  const int hit_any = block_any(hit);
+  const bool viol = TP::load(s, im, y0, x0, first);
+  TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.spin_limit, vs, hit);
+  TP::store(s, im, y0, x0);
+  const uint32_t act = TP::activation_mask(s);
   if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&ctl->visits, 1ull);
-    if (s.viol) atomicOr(&ctl->status, ST_MARKER_GT_MASK);
-    if (hit_any) atomicOr(&ctl->status, ST_INTERNAL);
-    flush_stats(ctl, s.npush, s.nround, s.novf);
+    WorkerStats ws;
+    ws.add(vs);
+    ws.visits = 1;
+    if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
+    if (hit) atomicOr((int*)&ctl->status.v, ST_INTERNAL);
+    ws.flush(ctl);
     bool any = false;
     for (int d = 0; d < 9; ++d) {
-      if (!s.act[d]) continue;
+      if (!((act >> d) & 1u)) continue;
       const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
       if (ny < 0 || ny >= im.tiles_y || nx < 0 || nx >= im.tiles_x) continue;
       act_next[im.tile_base + ny * im.tiles_x + nx] = 1;
@@ -780,10 +932,9 @@ __global__ __launch_bounds__(NT) void k_round(DevImage one, const DevImage* __re
 
 // ------------------------------------------------------------ small kernels
 
-// Reset the control block and per-tile state; the queue receives every tile
-// in the order slot -> (slot * mul + add) mod ntiles (mul coprime to ntiles).
+// Reset the control block, per-tile state and the queue rings.
 __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uint8_t* visited,
-                       uint8_t* active, uint32_t mul, uint32_t add) {
+                       uint8_t* active) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = gid; i < kp.ntiles; i += stride) {
@@ -792,20 +943,18 @@ __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uin
     if (active) active[i] = 1;
   }
   if (queue) {
-    for (int64_t i = gid; i < (int64_t)kp.qcap; i += stride) {
-      int v = -1;
-      if (i < kp.ntiles)
-        v = (int)(((unsigned long long)i * mul + add) % (unsigned long long)kp.ntiles);
-      queue[i] = v;
-    }
+    const int64_t n = (int64_t)kp.nq * kp.qcap;
+    for (int64_t i = gid; i < n; i += stride) queue[i] = kSlotEmpty;
   }
-  if (gid == 0) {
-    DevCtl c = {};
-    c.q_head = 0;
-    c.q_tail = queue ? (uint32_t)kp.ntiles : 0u;
-    c.pending = state ? (int32_t)kp.ntiles : 0;
-    c.q_high = c.q_tail;
-    *ctl = c;
+  // the control block: one 32-bit word per thread of the first workgroup
+  uint32_t* w = (uint32_t*)ctl;
+  const int nw = (int)(sizeof(DevCtl) / 4);
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x < kMaxQueues && queue && threadIdx.x < kp.nq)
+      ctl->tail[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
+    if (threadIdx.x == 0) ctl->pending.v = state ? (uint32_t)kp.ntiles : 0u;
   }
 }
 
@@ -826,6 +975,8 @@ __global__ __launch_bounds__(256) void k_copy(uint4* __restrict__ dst,
   X(uint8_t, 8, 64)      \
   X(uint8_t, 4, 128)     \
   X(uint8_t, 8, 128)     \
+  X(int32_t, 4, 32)      \
+  X(int32_t, 8, 32)      \
   X(int32_t, 4, 64)      \
   X(int32_t, 8, 64)
 
@@ -843,11 +994,11 @@ bool variant_supported(const Variant& v) {
 hipError_t launch_persistent(const Variant& v, const DevImage& one, const DevImage* imgs,
                              const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
                              uint8_t* visited, int grid, hipStream_t st) {
-#define X(T, C, H)                                                                              \
-  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                       \
-    hipLaunchKernelGGL((k_persistent<T, C, H>), dim3(grid), dim3(NT), 0, st, one, imgs, kp, ctl, \
-                       queue, state, visited);                                                  \
-    return hipGetLastError();                                                                   \
+#define X(T, C, H)                                                                          \
+  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                   \
+    hipLaunchKernelGGL((k_persistent<T, C, H>), dim3(grid), dim3(kThreads), 0, st, one,     \
+                       imgs, kp, ctl, queue, state, visited);                               \
+    return hipGetLastError();                                                               \
   }
   IWPP_VARIANTS(X)
 #undef X
@@ -859,11 +1010,11 @@ hipError_t launch_round(const Variant& v, const DevImage& one, const DevImage* i
                         uint8_t* visited, hipStream_t st) {
   const int64_t per = (kp.ntiles + 7) / 8;
   const unsigned grid = (unsigned)(per * 8);
-#define X(T, C, H)                                                                           \
-  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                    \
-    hipLaunchKernelGGL((k_round<T, C, H>), dim3(grid), dim3(NT), 0, st, one, imgs, kp, ctl, \
-                       act_cur, act_next, visited);                                          \
-    return hipGetLastError();                                                                \
+#define X(T, C, H)                                                                            \
+  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                     \
+    hipLaunchKernelGGL((k_round<T, C, H>), dim3(grid), dim3(kThreads), 0, st, one, imgs, kp, \
+                       ctl, act_cur, act_next, visited);                                      \
+    return hipGetLastError();                                                                 \
   }
   IWPP_VARIANTS(X)
 #undef X
@@ -872,12 +1023,12 @@ hipError_t launch_round(const Variant& v, const DevImage& one, const DevImage* i
 
 int persistent_blocks_per_cu(const Variant& v) {
   int nb = 0;
-#define X(T, C, H)                                                                      \
-  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {               \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<T, C, H>, NT, 0) \
-        != hipSuccess)                                                                  \
-      return 0;                                                                         \
-    return nb;                                                                          \
+#define X(T, C, H)                                                                            \
+  if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                     \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<T, C, H>, kThreads, 0) \
+        != hipSuccess)                                                                        \
+      return 0;                                                                               \
+    return nb;                                                                                \
   }
   IWPP_VARIANTS(X)
 #undef X
@@ -885,14 +1036,14 @@ int persistent_blocks_per_cu(const Variant& v) {
 }
 
 hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
-                       uint8_t* visited, uint8_t* active, uint32_t order_mul, uint32_t order_add,
-                       hipStream_t st) {
-  int64_t work = kp.ntiles > (int64_t)kp.qcap ? kp.ntiles : (int64_t)kp.qcap;
+                       uint8_t* visited, uint8_t* active, hipStream_t st) {
+  const int64_t ring = queue ? (int64_t)kp.nq * kp.qcap : 0;
+  int64_t work = kp.ntiles > ring ? kp.ntiles : ring;
   int64_t blocks = (work + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, st, kp, ctl, queue, state,
-                     visited, active, order_mul, order_add);
+                     visited, active);
   return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ struct Resolved {
   int64_t max_visits;
   uint32_t order_seed;
   uint32_t spin_limit;
+  int timing;
+  int seed_queue_max;
 };
 
 // Device buffers of one launch context (a stream workspace, a batch plan or a
@@ -37,6 +39,9 @@ struct Buffers {
   int descs_cap = 0;
   hipStream_t stream_owner = nullptr;
   bool incomplete_rounds = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // kernel timing (created on demand)
+  bool timed = false;                     // last enqueue recorded ev[0..1]
+  double rounds_ms = 0;                   // host-driven rounds: summed kernel time
   int ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds);
   void release();
 };
@@ -47,10 +52,13 @@ int check_image(const iwpp_image* im, int dtype);
 int check_common(int dtype, int conn, uint32_t flags);
 DevImage make_dev_image(const iwpp_image& im, int tile_h, int64_t tile_base);
 int device_grid(const Variant& v, int64_t ntiles, int want, int* grid);
+int plan_queues(const Variant& v, const Resolved& rp, int64_t ntiles, int nimg,
+                const DevImage& one, int* grid, KParams* kp);
 int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& one,
             const DevImage* d_imgs, int nimg, int64_t ntiles, hipStream_t st, int64_t* launches);
 int status_of(const DevCtl& c, uint32_t flags, bool incomplete_rounds);
 void fill_stats(const DevCtl& c, int status, int nimg, int64_t ntiles, int64_t launches,
                 iwpp_stats* s);
+double kernel_ms(Buffers& b);
 
 }  // namespace iwpp

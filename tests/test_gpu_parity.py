@@ -122,21 +122,23 @@ def test_row_pitch(iwpp):
 
 @pytest.mark.parametrize("params", [
     {"mode": 1}, {"sweeps": -1}, {"sweeps": 1}, {"sweeps": 4}, {"tile_h": 128},
-    {"order_seed": 7}, {"order_seed": 12345, "sweeps": -1}, {"grid": 3}, {"grid": 1},
-    {"mode": 1, "sweeps": -1}, {"mode": 1, "tile_h": 128},
+    {"tile_h": 32}, {"order_seed": 7}, {"order_seed": 12345, "sweeps": -1}, {"grid": 3},
+    {"grid": 1}, {"mode": 1, "sweeps": -1}, {"mode": 1, "tile_h": 128}, {"seed_queue": -1},
+    {"seed_queue": 100000}, {"seed_queue": 100000, "sweeps": -1},
 ])
 def test_parameters_do_not_change_the_result(iwpp, params):
-    for (I, J, conn) in [(*synth.c2(H=600, W=520), 8), (*synth.c1(H=400, W=333), 4)]:
-        if params.get("tile_h") == 128 and I.dtype != np.uint8:
-            continue
-        announce("params %s %dx%d conn %d" % (params, I.shape[0], I.shape[1], conn))
+    th = params.get("tile_h")
+    u8_ok = th in (None, 64, 128)
+    i32_ok = th in (None, 32, 64)
+    cases = []
+    if u8_ok:
+        cases += [(*synth.c2(H=600, W=520), 8), (*synth.c1(H=400, W=333), 4)]
+    if i32_ok:
+        cases += [(*synth.c3_i32(H=300, W=450), 8), (*synth.c3_i32(H=131, W=77), 4)]
+    for (I, J, conn) in cases:
+        announce("params %s %s %dx%d conn %d" % (params, I.dtype, I.shape[0], I.shape[1], conn))
         got, _ = run(iwpp, I, J, conn, params=params)
         same(got, expect(I, J, conn), "params %s" % params)
-    I, J = synth.c3_i32(H=300, W=450)
-    if params.get("tile_h") != 128:
-        announce("params %s i32 300x450" % (params,))
-        got, _ = run(iwpp, I, J, 8, params=params)
-        same(got, expect(I, J, 8), "params %s i32" % params)
 
 
 # ------------------------------------------------------------------ errors / restart
