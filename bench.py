@@ -189,7 +189,7 @@ def bench_single(args, torch, iwpp):
         "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
                                              "pixels_queued", "queue_overflows", "reprocessed",
                                              "queue_iterations", "idle_ms", "load_ms", "solve_ms",
-                                             "store_ms")},
+                                             "store_ms", "sync_ms")},
         "ms_min": round(float(np.min(call_ms)), 4), "ms_cv": round(float(np.std(call_ms) / ms), 4),
         "wall_ms_per_step_incl_restore": round(wall * 1e3 / args.steps, 4),
     }
@@ -282,6 +282,97 @@ def bench_batched(args, torch, iwpp):
     }
 
 
+def bench_served(args, torch, iwpp):
+    """Poisson arrivals into the continuous-batching server.  A pool of
+    distinct requests is generated once and kept on the device; each arrival
+    picks one, gets its own working marker (filled from the pristine copy by
+    the server on the device) and is submitted at its arrival time."""
+    import threading
+
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    pool = synth.c5_pool(seed=4, n=args.pool)
+    log("generated %d pool requests in %.1f s" % (len(pool), time.perf_counter() - t0))
+    masks = [torch.from_numpy(I).to(dev) for I, J, _ in pool]
+    pristine = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
+    px = [I.size for I, J, _ in pool]
+    del pool
+    copies = 8
+    work = [[torch.empty_like(p) for _ in range(copies)] for p in pristine]
+    times, idx = synth.c5_arrivals(seed=4, rate=args.rate, duration=args.duration, pool=len(masks))
+    srv = iwpp.Server(int(args.budget_gb * 1e9), "u8", 8, streams=args.streams,
+                      max_inflight=args.max_inflight)
+    # warm the kernels and the slots
+    for k in range(min(8, len(masks))):
+        srv.wait(srv.submit(work[k][0], masks[k], marker_init=pristine[k]))
+    torch.cuda.synchronize()
+    lat, done_px, errors = [], [0], [0]
+    lock = threading.Lock()
+
+    def waiter(q):
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            t, k, ev = item
+            rc, l = srv.wait(t)
+            with lock:
+                if rc != iwpp.OK:
+                    errors[0] += 1
+                lat.append(l)
+                done_px[0] += px[k]
+            ev.set()  # the working marker may be reused
+
+    import queue as _queue
+
+    qq = _queue.Queue()
+    th = threading.Thread(target=waiter, args=(qq,), daemon=True)
+    th.start()
+    busy = {}  # (pool index, copy) -> event set when its last request was collected
+    uses = [0] * len(masks)
+    late = 0
+    start = time.perf_counter()
+    for ta, k in zip(times, idx):
+        k = int(k)
+        delay = start + ta - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        elif delay < -0.005:
+            late += 1
+        key = (k, uses[k] % copies)
+        uses[k] += 1
+        prev = busy.get(key)
+        if prev is not None:
+            prev.wait()
+        ev = threading.Event()
+        t = srv.submit(work[k][key[1]], masks[k], marker_init=pristine[k])
+        busy[key] = ev
+        qq.put((t, k, ev))
+    qq.put(None)
+    th.join()
+    wall = time.perf_counter() - start
+    srv.close()
+    lat_ms = sorted(x / 1e3 for x in lat)
+    value = done_px[0] / wall / 1e6
+    return {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": len(lat), "warmup": 8, "ms_per_step": round(wall * 1e3 / max(1, len(lat)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "c5", "rate_req_s": args.rate, "duration_s": args.duration,
+                   "pool": len(masks), "streams": args.streams,
+                   "max_inflight": args.max_inflight, "budget_gb": args.budget_gb, "conn": 8},
+        "served": {"requests": len(lat), "errors": errors[0], "req_s": round(len(lat) / wall, 1),
+                   "offered_req_s": round(len(times) / args.duration, 1),
+                   "late_arrivals": late,
+                   "p50_ms": round(lat_ms[len(lat_ms) // 2], 3),
+                   "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 3),
+                   "max_ms": round(lat_ms[-1], 3), "wall_s": round(wall, 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +385,12 @@ def main():
     ap.add_argument("--mode", type=int, default=None)
     ap.add_argument("--seed-queue", dest="seed_queue", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrivals per second")
+    ap.add_argument("--duration", type=float, default=3.0, help="c5 seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=64, help="c5 distinct requests")
+    ap.add_argument("--streams", type=int, default=4, help="c5 server launch slots")
+    ap.add_argument("--max-inflight", dest="max_inflight", type=int, default=512)
+    ap.add_argument("--budget-gb", dest="budget_gb", type=float, default=64.0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run the library copy kernel on this many MiB (profiler scaling)")
@@ -329,9 +426,7 @@ def main():
     if args.workload == "c4":
         res = bench_batched(args, torch, iwpp)
     elif args.workload == "c5":
-        import serve
-
-        res = serve.bench_served(args, torch, iwpp, METRIC)
+        res = bench_served(args, torch, iwpp)
     else:
         res = bench_single(args, torch, iwpp)
     if not args.no_cpu_baseline:

@@ -89,8 +89,9 @@ typedef struct iwpp_stats {
                               iwpp_params.timing was set, else 0                  */
   int64_t queue_iterations; /* identify/propagate pairs over all tile queues      */
   /* wavefront-milliseconds summed over the persistent workers: waiting for a
-     tile, loading tiles, solving them, storing and publishing them */
-  double idle_ms, load_ms, solve_ms, store_ms;
+     tile, loading tiles, solving them, storing them, publishing them (release
+     fence and tile-state updates) */
+  double idle_ms, load_ms, solve_ms, store_ms, sync_ms;
 } iwpp_stats;
 
 /*
@@ -195,21 +196,32 @@ int iwpp_autotune(const iwpp_image *img, int dtype, int conn, iwpp_stream_t stre
                   iwpp_params *best);
 
 /*
- * Continuous-batching server.  Requests are admitted while the device bytes
- * they hold (marker, mask and their share of queue and state) fit in
- * `budget_bytes` and fewer than `max_inflight` launches are running;
- * requests admitted together form one persistent launch, and launches of
- * different admissions overlap on `streams` HIP streams.
- *   submit: the image buffers are the caller's and must stay valid until
- *           the request completes; returns IWPP_E_BUDGET if the request alone
- *           exceeds the budget.  Non-blocking.
- *   wait:   blocks until the request finishes (timeout_us < 0: forever) and
- *           returns its status; latency_us receives completion - submit time.
+ * Continuous-batching server for reconstructions whose buffers already live
+ * on the device (a serving loop built around the same kernels; it has no
+ * counterpart in the paper).  A dispatcher thread admits pending requests in
+ * arrival order while the device bytes they hold (marker, mask and their
+ * share of tile state and queues) fit in `budget_bytes` and fewer than
+ * `max_inflight` requests are unfinished.  The requests admitted together
+ * form one batched persistent launch on a free slot of `streams` HIP
+ * streams; launches on different slots overlap on the device, so requests
+ * that arrive while others run start as soon as a slot and memory free up.
+ *   submit: non-blocking.  The buffers are the caller's and must stay valid
+ *           until the request is waited for.  If `marker_init` is not NULL it
+ *           is a device image with the marker's shape and row pitch that is
+ *           copied into the marker (on the launch stream) before the
+ *           reconstruction.  Returns IWPP_E_BUDGET if the request alone
+ *           exceeds the budget.
+ *   wait:   blocks until the request finishes (timeout_us < 0: forever;
+ *           IWPP_E_TIMEOUT otherwise) and returns its status (the status of
+ *           the launch it ran in); latency_us receives completion - submit
+ *           time in microseconds.  A ticket can be waited for once.
+ *   destroy: finishes every admitted and pending request, then frees.
  */
 typedef struct iwpp_server iwpp_server;
 int iwpp_server_create(size_t budget_bytes, int dtype, int conn, int streams,
                        int max_inflight, iwpp_server **out);
-int iwpp_server_submit(iwpp_server *s, const iwpp_image *img, uint64_t *ticket);
+int iwpp_server_submit(iwpp_server *s, const iwpp_image *img, const void *marker_init,
+                       uint64_t *ticket);
 int iwpp_server_wait(iwpp_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
 int iwpp_server_destroy(iwpp_server *s);
 

@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("requeued", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("queue_iterations", ctypes.c_int64),
                 ("idle_ms", ctypes.c_double), ("load_ms", ctypes.c_double),
-                ("solve_ms", ctypes.c_double), ("store_ms", ctypes.c_double)]
+                ("solve_ms", ctypes.c_double), ("store_ms", ctypes.c_double),
+                ("sync_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: (float if t is ctypes.c_double else int)(getattr(self, k))
@@ -100,7 +101,7 @@ def _load():
         "iwpp_batch_destroy": ([vp], i32),
         "iwpp_autotune": ([P(Image), i32, i32, vp, P(Params)], i32),
         "iwpp_server_create": ([ctypes.c_size_t, i32, i32, i32, i32, P(vp)], i32),
-        "iwpp_server_submit": ([vp, P(Image), P(ctypes.c_uint64)], i32),
+        "iwpp_server_submit": ([vp, P(Image), vp, P(ctypes.c_uint64)], i32),
         "iwpp_server_wait": ([vp, ctypes.c_uint64, i64, P(ctypes.c_double)], i32),
         "iwpp_server_destroy": ([vp], i32),
         "iwpp_release_workspace": ([], i32),
@@ -287,13 +288,21 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, marker, mask) -> int:
+    def submit(self, marker, mask, marker_init=None) -> int:
+        """Queue R_mask(marker) in place; if `marker_init` is given it is
+        copied into `marker` on the device first."""
         im, _ = _image(marker, mask)
+        init = None
+        if marker_init is not None:
+            if marker_init.shape != marker.shape or marker_init.stride() != marker.stride() \
+                    or marker_init.dtype != marker.dtype or marker_init.device != marker.device:
+                raise ValueError("marker_init must match the marker's shape, pitch and dtype")
+            init = marker_init.data_ptr()
         t = ctypes.c_uint64()
-        rc = _load().iwpp_server_submit(self._h, ctypes.byref(im), ctypes.byref(t))
+        rc = _load().iwpp_server_submit(self._h, ctypes.byref(im), init, ctypes.byref(t))
         if rc != OK:
             raise IwppError(rc, "iwpp_server_submit")
-        self._keep[t.value] = (marker, mask)
+        self._keep[t.value] = (marker, mask, marker_init)
         return t.value
 
     def wait(self, ticket: int, timeout_us: int = -1) -> tuple[int, float]:

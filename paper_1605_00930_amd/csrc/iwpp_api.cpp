@@ -437,6 +437,7 @@ void fill_stats(const DevCtl& c, int status, int nimg, int64_t ntiles, int64_t l
   s->load_ms = (double)c.t_load / khz;
   s->solve_ms = (double)c.t_solve / khz;
   s->store_ms = (double)c.t_store / khz;
+  s->sync_ms = (double)c.t_sync / khz;
 }
 
 double kernel_ms(Buffers& b) {

@@ -42,8 +42,9 @@ struct DevCtl {
   int32_t active_any;  // host-driven rounds: some tile was activated
   int32_t pad0;
   // wavefront time (wall_clock64 ticks, summed over workers) spent waiting
-  // for work, loading tiles, solving tiles and storing / publishing them
-  uint64_t t_idle, t_load, t_solve, t_store;
+  // for work, loading tiles, solving tiles, storing them and publishing them
+  // (release fence + tile-state updates)
+  uint64_t t_idle, t_load, t_solve, t_store, t_sync;
 };
 
 enum : int32_t {

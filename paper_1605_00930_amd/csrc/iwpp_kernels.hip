@@ -630,7 +630,7 @@ __device__ __forceinline__ void add64(uint64_t* p, uint64_t v) {
 // Per-worker totals, flushed once when the worker exits.
 struct WorkerStats {
   uint64_t pushes = 0, rounds = 0, iters = 0, ovf = 0, visits = 0, reproc = 0, requeued = 0;
-  uint64_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0;
+  uint64_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0, t_sync = 0;
   __device__ void add(const VisitStats& v) {
     pushes += v.pushes;
     rounds += v.rounds;
@@ -649,6 +649,7 @@ struct WorkerStats {
     add64(&ctl->t_load, t_load);
     add64(&ctl->t_solve, t_solve);
     add64(&ctl->t_store, t_store);
+    add64(&ctl->t_sync, t_sync);
   }
 };
 
@@ -774,47 +775,53 @@ __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* s
   return v;
 }
 
-// Publish the end of a visit of tile t (lane 0 only; the wavefront has
-// executed an agent-scope release fence after writing the tile): ask the
-// neighbours in `act` for a visit, release t, and keep the pending count.
-// Returns 1 if t must be run again (a neighbour asked while it ran), 2 if
-// this visit completed the launch, 0 otherwise.
+// Publish the end of a visit of tile t (whole wavefront, after an
+// agent-scope release fence that follows the tile's write-back): ask the
+// neighbours in `act` for a visit (lane d handles neighbour d, so the nine
+// state updates share one round trip), release t, keep the pending count and
+// queue the neighbours that were idle.  Returns 1 if t must be run again (a
+// neighbour asked while it ran), 2 if this visit completed the launch, 0
+// otherwise.
 __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
                        const DevImage& im, int64_t ty, int64_t tx, uint32_t act,
                        WorkerStats& ws) {
-  int fresh[8];
-  int nfresh = 0;
-  for (int d = 0; d < 9; ++d) {
-    if (!((act >> d) & 1u)) continue;
+  const int d = threadIdx.x;
+  int n = -1;
+  if (d < 9 && ((act >> d) & 1u)) {
     const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
-    if (ny < 0 || ny >= im.tiles_y || nx < 0 || nx >= im.tiles_x) continue;
-    const int n = (int)(im.tile_base + ny * im.tiles_x + nx);
-    const uint32_t old =
-        __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0u) fresh[nfresh++] = n;  // was idle: this wavefront enqueues it
+    if (ny >= 0 && ny < im.tiles_y && nx >= 0 && nx < im.tiles_x)
+      n = (int)(im.tile_base + ny * im.tiles_x + nx);
   }
-  uint32_t expect = TS_RUNNING;
-  const bool released = __hip_atomic_compare_exchange_strong(
-      &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // count the new tiles before they become visible; the running tile keeps
-  // the count above zero until this update
-  const int delta = nfresh - (released ? 1 : 0);
-  int result = 0;
-  if (delta != 0) {
-    const int old = atomicAdd((int*)&ctl->pending.v, delta);
-    if (old + delta == 0) result = 2;
+  bool fresh = false;  // was idle: this wavefront enqueues it
+  if (n >= 0)
+    fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  const int nfresh = __popcll(__ballot(fresh));
+  int res = 0;
+  if (d == 0) {
+    uint32_t expect = TS_RUNNING;
+    const bool released = __hip_atomic_compare_exchange_strong(
+        &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // count the new tiles before they become visible; the running tile keeps
+    // the count above zero until this update
+    const int delta = nfresh - (released ? 1 : 0);
+    if (delta != 0) {
+      const int old = atomicAdd((int*)&ctl->pending.v, delta);
+      if (old + delta == 0) res = 2;
+    }
+    if (!released) {
+      // running | pending: take the request (acquire: the neighbour's new
+      // border becomes visible) and run again
+      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      ws.reproc++;
+      ws.visits++;
+      res = 1;
+    }
   }
-  for (int k = 0; k < nfresh; ++k) queue_push(ctl, queue, kp, fresh[k]);
+  res = __builtin_amdgcn_readfirstlane(res);
+  if (fresh) queue_push(ctl, queue, kp, n);
   ws.requeued += nfresh;
-  if (!released) {
-    // running | pending: take the request (acquire: the neighbour's new
-    // border becomes visible) and run again
-    __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    ws.reproc++;
-    ws.visits++;
-    result = 1;
-  }
-  return result;
+  return res;
 }
 
 template <typename T, int CONN, int TH>
@@ -853,20 +860,20 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
     for (;;) {
       TP::store(s, im, y0, x0);
       const uint32_t act = TP::activation_mask(s);
-      // publish the tile before anyone is told about it
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      int res = 0;
+      uint64_t c3b = now();
+      ws.t_store += c3b - c3;
       if (lead) {
         if (first) visited[t] = 1;
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         ws.add(vs);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
-        res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
       }
-      res = __builtin_amdgcn_readfirstlane(res);
+      // publish the tile before anyone is told about it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
       if (res == 2) stop_all(ctl, queue, kp, grid);
       uint64_t c4 = now();
-      ws.t_store += c4 - c3;
+      ws.t_sync += c4 - c3b;
       if (res != 1) break;
       // a neighbour changed while this tile ran: reload the halo, continue
       vs = VisitStats();

@@ -1,0 +1,112 @@
+"""GPU tests of the continuous-batching server: every result equals the CPU
+oracle and the same request run alone, whatever else shares the device."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def iwpp():
+    import torch
+
+    import paper_1605_00930_amd as lib
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib._load()
+    return lib
+
+
+def _pool(n, lo, hi, seed=4):
+    return synth.c5_pool(seed=seed, n=n, lo=lo, hi=hi)
+
+
+def _expect(I, J):
+    rc, R = oracle.reconstruct(J, I, 8)
+    assert rc == oracle.OK
+    return R
+
+
+def test_server_mix_equals_alone_equals_oracle(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    pool = _pool(24, 40, 600)
+    masks = [torch.from_numpy(I).to(dev) for I, J, _ in pool]
+    pristine = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
+    want = [_expect(I, J) for I, J, _ in pool]
+    print("[gpu-case] server mix of 24 requests, 3 copies each", flush=True)
+    srv = iwpp.Server(8 << 30, "u8", 8, streams=4, max_inflight=64)
+    outs, tickets = [], []
+    for rep in range(3):  # many requests in flight at once
+        for k in range(len(pool)):
+            out = torch.empty_like(pristine[k])
+            outs.append((k, out))
+            tickets.append(srv.submit(out, masks[k], marker_init=pristine[k]))
+    lats = []
+    for t in tickets:
+        rc, lat = srv.wait(t)
+        assert rc == iwpp.OK
+        lats.append(lat)
+    for k, out in outs:
+        np.testing.assert_array_equal(out.cpu().numpy(), want[k])
+    # alone: one request at a time through the server and through the plain call
+    for k in range(0, len(pool), 5):
+        out = pristine[k].clone()
+        rc, _ = srv.wait(srv.submit(out, masks[k]))
+        assert rc == iwpp.OK
+        np.testing.assert_array_equal(out.cpu().numpy(), want[k])
+        out = pristine[k].clone()
+        iwpp.reconstruct(out, masks[k], 8)
+        np.testing.assert_array_equal(out.cpu().numpy(), want[k])
+    srv.close()
+    assert all(l > 0 for l in lats)
+
+
+def test_server_budget_admission(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    pool = _pool(6, 200, 300, seed=9)
+    masks = [torch.from_numpy(I).to(dev) for I, J, _ in pool]
+    pristine = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
+    biggest = max(2 * I.size for I, J, _ in pool)
+    print("[gpu-case] server with a budget for about one request", flush=True)
+    # room for about one request at a time: admission has to wait
+    srv = iwpp.Server(int(biggest * 1.5) + (1 << 16), "u8", 8, streams=2, max_inflight=8)
+    outs = [p.clone() for p in pristine]
+    tickets = [srv.submit(o, m) for o, m in zip(outs, masks)]
+    for t in tickets:
+        rc, _ = srv.wait(t)
+        assert rc == iwpp.OK
+    for (I, J, _), o in zip(pool, outs):
+        np.testing.assert_array_equal(o.cpu().numpy(), _expect(I, J))
+    # a request that can never fit is refused at submit time
+    big = torch.zeros((2000, 2000), dtype=torch.uint8, device=dev)
+    with pytest.raises(iwpp.IwppError) as e:
+        srv.submit(big, big.clone())
+    assert e.value.code == iwpp.E_BUDGET
+    srv.close()
+
+
+def test_server_wait_timeout_and_unknown_ticket(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    I, J = synth.c2(H=256, W=256)
+    srv = iwpp.Server(1 << 30, "u8", 8, streams=1, max_inflight=4)
+    m = torch.from_numpy(I).to(dev)
+    o = torch.from_numpy(J).to(dev)
+    t = srv.submit(o, m)
+    rc, _ = srv.wait(t, timeout_us=10_000_000)
+    assert rc == iwpp.OK
+    rc, _ = srv.wait(t)  # already collected
+    assert rc == iwpp.E_ARG
+    srv.close()
+    np.testing.assert_array_equal(o.cpu().numpy(), _expect(I, J))
