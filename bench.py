@@ -56,9 +56,9 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic(workload: str):
-    """HBM bytes per launch from profiles/pmc_<workload>.txt, or None if the
+    """HBM bytes per launch from profiles/traffic_k_persistent_<workload>.txt, or None if the
     summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s.txt" % workload)
+    path = os.path.join(ROOT, "profiles", "traffic_k_persistent_%s.txt" % workload)
     if not os.path.exists(path):
         return None
     kv = {}
