@@ -159,78 +159,77 @@ struct Tile {
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     wsync();
     bool viol = false;
-    // Main part: lanes 0..63 cover padded columns 0..63, i.e. the left halo
-    // column and tile columns 0..62, one row per step, B rows in flight.
-    {
-      const int64_t gx = x0 + lane() - 1;
-      const bool c_in = gx >= 0 && gx < im.W;
-      constexpr int B = 16;
-      for (int yb = 0; yb < G::ROWS; yb += B) {
-        int j[B], i[B];
-        const int64_t gy0 = y0 + yb - 1;
-        const T* pj = gJ + gy0 * im.ld + gx;
-        const T* pi = gI + gy0 * im.ld + gx;
+    // Lanes 0..63 cover padded columns 0..63 (the left halo column and tile
+    // columns 0..62), B rows per batch; padded columns 64 and 65 (tile column
+    // 63 and the right halo column) of all rows are spread over the lanes and
+    // issued with the first batch.  Two batches cover the tile.
+    constexpr int B = G::ROWS / 2 + 1 < 33 ? G::ROWS / 2 + 1 : 33;
+    constexpr int NE = 2 * G::ROWS;
+    constexpr int K = (NE + 63) / 64;
+    const int64_t gx = x0 + lane() - 1;
+    const bool c_in = gx >= 0 && gx < im.W;
+    int ej[K], ei[K];
+#pragma unroll 1
+    for (int yb = 0; yb < G::ROWS; yb += B) {
+      int j[B], i[B];
+      const int64_t gy0 = y0 + yb - 1;
+      const T* pj = gJ + gy0 * im.ld + gx;
+      const T* pi = gI + gy0 * im.ld + gx;
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int64_t gy = gy0 + k;
-          j[k] = i[k] = LO;
-          if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
-            j[k] = (int)pj[k * im.ld];
-            i[k] = (int)pi[k * im.ld];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int yy = yb + k;
-          if (yy >= G::ROWS) continue;
-          int a = j[k];
-          const int b = i[k];
-          if (a > b) {
-            if (yy >= 1 && yy <= TH && lane() >= 1) {
-              viol = viol || first;
-              s.rowdirty[yy - 1] = 1;  // the clamped value must reach memory
-            }
-            a = b;
-          }
-          s.J[yy * G::P + lane()] = (T)a;
-          s.I[yy * G::P + lane()] = (T)b;
-        }
-      }
-    }
-    // Padded columns 64 and 65 (tile column 63 and the right halo column) of
-    // every padded row: 2 * ROWS elements spread over the lanes.
-    {
-      constexpr int NE = 2 * G::ROWS;
-      constexpr int K = (NE + 63) / 64;
-      int j[K], i[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int e = lane() + 64 * k;
-        const int yy = e >> 1, c = 64 + (e & 1);
-        const int64_t gy = y0 + yy - 1, gx = x0 + c - 1;
+      for (int k = 0; k < B; ++k) {
+        const int64_t gy = gy0 + k;
         j[k] = i[k] = LO;
-        if (e < NE && gy >= 0 && gy < im.H && gx < im.W) {
-          j[k] = (int)gJ[gy * im.ld + gx];
-          i[k] = (int)gI[gy * im.ld + gx];
+        if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
+          j[k] = (int)pj[k * im.ld];
+          i[k] = (int)pi[k * im.ld];
+        }
+      }
+      if (yb == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int e = lane() + 64 * k;
+          const int yy = e >> 1, c = 64 + (e & 1);
+          const int64_t ey = y0 + yy - 1, ex = x0 + c - 1;
+          ej[k] = ei[k] = LO;
+          if (e < NE && ey >= 0 && ey < im.H && ex < im.W) {
+            ej[k] = (int)gJ[ey * im.ld + ex];
+            ei[k] = (int)gI[ey * im.ld + ex];
+          }
         }
       }
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int e = lane() + 64 * k;
-        if (e >= NE) continue;
-        const int yy = e >> 1, c = 64 + (e & 1);
+      for (int k = 0; k < B; ++k) {
+        const int yy = yb + k;
+        if (yy >= G::ROWS) continue;
         int a = j[k];
         const int b = i[k];
         if (a > b) {
-          if (yy >= 1 && yy <= TH && c == 64) {
+          if (yy >= 1 && yy <= TH && lane() >= 1) {
             viol = viol || first;
-            s.rowdirty[yy - 1] = 1;
+            s.rowdirty[yy - 1] = 1;  // the clamped value must reach memory
           }
           a = b;
         }
-        s.J[yy * G::P + c] = (T)a;
-        s.I[yy * G::P + c] = (T)b;
+        s.J[yy * G::P + lane()] = (T)a;
+        s.I[yy * G::P + lane()] = (T)b;
       }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = lane() + 64 * k;
+      if (e >= NE) continue;
+      const int yy = e >> 1, c = 64 + (e & 1);
+      int a = ej[k];
+      const int b = ei[k];
+      if (a > b) {
+        if (yy >= 1 && yy <= TH && c == 64) {
+          viol = viol || first;
+          s.rowdirty[yy - 1] = 1;
+        }
+        a = b;
+      }
+      s.J[yy * G::P + c] = (T)a;
+      s.I[yy * G::P + c] = (T)b;
     }
     wsync();
     snapshot_border(s);
@@ -279,6 +278,9 @@ struct Tile {
     wsync();
   }
 
+  // Write one marker pixel back to memory.
+  __device__ static void put(T* p, T v) { *p = v; }
+
   __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0) {
     T* __restrict__ gJ = (T*)im.J;
     const int64_t gx = x0 + lane();
@@ -290,103 +292,138 @@ struct Tile {
         const int y = g + __builtin_ctzll(rows);
         rows &= rows - 1;
         const int64_t gy = y0 + y;
-        if (gy < im.H && col_in) gJ[gy * im.ld + gx] = s.J[G::at(y, lane())];
+        if (gy < im.H && col_in) put(&gJ[gy * im.ld + gx], s.J[G::at(y, lane())]);
       }
     }
   }
 
   // ---------------------------------------------------------- scans
+  // The passes keep a register chain along the walking direction.  Rows (or
+  // columns) are loaded B at a time before they are used, so LDS latency is
+  // paid once per batch instead of once per step; every pixel of a pass has a
+  // single writer, so loading ahead is safe.  Changed rows are collected as
+  // ballot bits in `d` (wave-uniform) and written to rowdirty by the caller.
+  static constexpr int B = 16;
+
+  __device__ static void mark_rows(uint64_t& d0, uint64_t& d1, int y) {
+    if (y < 64)
+      d0 |= 1ull << y;
+    else
+      d1 |= 1ull << (y - 64);
+  }
+
   // Downward (D = +1) or upward (D = -1) pass; lane = column.
   template <int D>
-  __device__ static bool pass_vert(L& s) {
+  __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
-    const int y0 = D > 0 ? 0 : TH - 1;
-    int pc = jv(s, y0 - D, x);
+    const int ys = D > 0 ? 0 : TH - 1;
+    int pc = jv(s, ys - D, x);
     int pl = LO, pr = LO;
     if (CONN == 8) {
-      pl = jv(s, y0 - D, x - 1);
-      pr = jv(s, y0 - D, x + 1);
+      pl = jv(s, ys - D, x - 1);
+      pr = jv(s, ys - D, x + 1);
     }
-    bool any = false;
-#pragma unroll 4
-    for (int k = 0; k < TH; ++k) {
-      const int y = y0 + D * k;
-      const int a = G::at(y, x);
-      const int j = (int)s.J[a], i = (int)s.I[a];
-      int m = imax(j, pc);
-      if (CONN == 8) m = imax(m, imax(pl, pr));
-      const int v = imin(m, i);
-      const bool c = v != j;
-      if (c) s.J[a] = (T)v;
-      if (__ballot(c)) {
-        if (x == 0) s.rowdirty[y] = 1;
-        any = true;
+    // the halo column a DPP shift brings into this lane: lane 0 reads the
+    // left halo, lane 63 the right halo (other lanes' values are unused)
+    const int fx = x == 0 ? -1 : TW;
+#pragma unroll 1
+    for (int kb = 0; kb < TH; kb += B) {
+      int jj[B], ii[B], ff[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int y = ys + D * (kb + k);
+        jj[k] = jv(s, y, x);
+        ii[k] = iv(s, y, x);
+        if (CONN == 8) ff[k] = jv(s, y, fx);
       }
-      pc = v;
-      if (CONN == 8) {
-        pl = from_left(v, jv(s, y, -1));
-        pr = from_right(v, jv(s, y, TW));
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        int m = imax(jj[k], pc);
+        if (CONN == 8) m = imax(m, imax(pl, pr));
+        const int v = imin(m, ii[k]);
+        if (__ballot(v != jj[k])) mark_rows(d0, d1, ys + D * (kb + k));
+        jj[k] = v;
+        pc = v;
+        if (CONN == 8) {
+          pl = from_left(v, ff[k]);
+          pr = from_right(v, ff[k]);
+        }
       }
+#pragma unroll
+      for (int k = 0; k < B; ++k) s.J[G::at(ys + D * (kb + k), x)] = (T)jj[k];
     }
-    return any;
   }
 
   // Rightward (D = +1) or leftward (D = -1) pass; lane = row of a 64-row
   // group, groups taken top to bottom.
   template <int D>
-  __device__ static bool pass_horz(L& s) {
-    bool any = false;
+  __device__ static void pass_horz(L& s, uint64_t& d0, uint64_t& d1) {
+#pragma unroll 1
     for (int g = 0; g < TH; g += 64) {
       const int nrows = TH - g < 64 ? TH - g : 64;  // 32-row tiles use half the lanes
-      const int y = g + lane();
       const bool live = lane() < nrows;
-      const int yc = live ? y : g;  // dead lanes shadow row g
-      const int x0 = D > 0 ? 0 : TW - 1;
-      int pc = jv(s, yc, x0 - D);
+      const int yc = live ? g + lane() : g;  // dead lanes shadow row g
+      const int xs = D > 0 ? 0 : TW - 1;
+      int pc = jv(s, yc, xs - D);
       int pu = LO, pd = LO;
       if (CONN == 8) {
-        pu = jv(s, yc - 1, x0 - D);
-        pd = jv(s, yc + 1, x0 - D);
+        pu = jv(s, yc - 1, xs - D);
+        pd = jv(s, yc + 1, xs - D);
       }
+      // lane 0 gets the row above the group, the last live lane the row below
+      const int fy = lane() == 0 ? g - 1 : g + nrows;
       bool dirty = false;
-#pragma unroll 4
-      for (int k = 0; k < TW; ++k) {
-        const int x = x0 + D * k;
-        const int a = G::at(yc, x);
-        const int j = (int)s.J[a], i = (int)s.I[a];
-        int m = imax(j, pc);
-        if (CONN == 8) m = imax(m, imax(pu, pd));
-        const int v = imin(m, i);
-        if (live && v != j) {
-          s.J[a] = (T)v;
-          dirty = true;
+#pragma unroll 1
+      for (int kb = 0; kb < TW; kb += B) {
+        int jj[B], ii[B], ff[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const int x = xs + D * (kb + k);
+          jj[k] = jv(s, yc, x);
+          ii[k] = iv(s, yc, x);
+          if (CONN == 8) ff[k] = jv(s, fy, x);
         }
-        pc = v;
-        if (CONN == 8) {
-          // row y-1 of this group comes from lane y-1; the group's edges read
-          // the neighbouring row from LDS (halo or another group)
-          pu = from_left(v, jv(s, g - 1, x));
-          pd = from_right(v, jv(s, g + nrows, x));
-          if (nrows < 64 && lane() == nrows - 1) pd = jv(s, g + nrows, x);
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          int m = imax(jj[k], pc);
+          if (CONN == 8) m = imax(m, imax(pu, pd));
+          const int v = imin(m, ii[k]);
+          dirty = dirty || v != jj[k];
+          jj[k] = v;
+          pc = v;
+          if (CONN == 8) {
+            pu = from_left(v, ff[k]);
+            pd = from_right(v, ff[k]);
+            if (nrows < 64 && lane() == nrows - 1) pd = ff[k];
+          }
+        }
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < B; ++k) s.J[G::at(yc, xs + D * (kb + k))] = (T)jj[k];
         }
       }
-      if (dirty) s.rowdirty[y] = 1;
-      any = __ballot(dirty) != 0 || any;
+      const uint64_t b = __ballot(live && dirty);
+      if (g == 0)
+        d0 |= b;
+      else
+        d1 |= b;
       wsync();
     }
-    return any;
   }
 
   // One round of the four passes; true if any pixel of the tile rose.
   __device__ static bool sweep_round(L& s, VisitStats& vs) {
-    bool c = pass_vert<+1>(s);
+    uint64_t d0 = 0, d1 = 0;
+    pass_vert<+1>(s, d0, d1);
     wsync();
-    c = pass_vert<-1>(s) || c;
+    pass_vert<-1>(s, d0, d1);
     wsync();
-    c = pass_horz<+1>(s) || c;
-    c = pass_horz<-1>(s) || c;
+    pass_horz<+1>(s, d0, d1);
+    pass_horz<-1>(s, d0, d1);
     vs.rounds++;
-    return c;
+    for (int y = lane(); y < TH; y += 64)
+      if ((y < 64 ? (d0 >> y) : (d1 >> (y - 64))) & 1ull) s.rowdirty[y] = 1;
+    return (d0 | d1) != 0;
   }
 
   // ---------------------------------------------------------- seeds
@@ -403,12 +440,18 @@ struct Tile {
   // Every pixel a neighbour can still raise goes to queue 0; returns its length.
   __device__ static int scan_receivers(L& s) {
     int n = 0;
+    constexpr int R = 8;
 #pragma unroll 1
-    for (int y = 0; y < TH; ++y) {
-      const int a = G::at(y, lane());
-      const int j = (int)s.J[a], i = (int)s.I[a];
-      const bool r = j < i && nbr_max(s, y, lane()) > j;
-      push(s, 0, n, r, y * TW + lane());
+    for (int yb = 0; yb < TH; yb += R) {
+      bool r[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int a = G::at(yb + k, lane());
+        const int j = (int)s.J[a], i = (int)s.I[a];
+        r[k] = j < i && nbr_max(s, yb + k, lane()) > j;
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) push(s, 0, n, r[k], (yb + k) * TW + lane());
     }
     wsync();
     return n;
@@ -493,7 +536,8 @@ struct Tile {
       }
       wsync();
       // identification: neighbours of risen pixels that can now be raised,
-      // each claimed once through the bitmap
+      // each claimed once through the bitmap (all reads, then all claims,
+      // then the compaction, so the LDS round trips overlap)
       int nn = 0;
 #pragma unroll 1
       for (int base = 0; base < n; base += 64) {
@@ -502,29 +546,34 @@ struct Tile {
         bool live = false;
         if (e < n) {
           const int q = s.q[0][e];
-          if (q & kRose) {
-            live = true;
-            idx = q & ~kRose;
-            jp = (int)s.J[G::at(idx / TW, idx % TW)];
-          }
+          live = (q & kRose) != 0;
+          idx = q & ~kRose;
         }
         const int y = idx / TW, x = idx % TW;
+        if (live) jp = (int)s.J[G::at(y, x)];
+        constexpr int ND = CONN;
+        int qi[ND], jq[ND], iq[ND];
+        bool cand[ND];
 #pragma unroll
-        for (int d = 0; d < 9; ++d) {
-          const int dy = d / 3 - 1, dx = d % 3 - 1;
-          if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
-          const int yy = y + dy, xx = x + dx;
-          bool win = false;
-          const int qi = yy * TW + xx;
-          if (live && yy >= 0 && yy < TH && xx >= 0 && xx < TW) {
-            const int a = G::at(yy, xx);
-            const int jq = (int)s.J[a];
-            if (jq < jp && jq < (int)s.I[a]) {
-              const uint32_t bit = 1u << (qi & 31);
-              win = !(atomicOr(&s.claim[qi >> 5], bit) & bit);
-            }
-          }
-          push(s, 1, nn, win, qi);
+        for (int k = 0; k < ND; ++k) {
+          const int d = CONN == 8 ? (k < 4 ? k : k + 1) : (k == 0 ? 1 : k == 1 ? 3 : k == 2 ? 5 : 7);
+          const int yy = y + d / 3 - 1, xx = x + d % 3 - 1;
+          cand[k] = live && yy >= 0 && yy < TH && xx >= 0 && xx < TW;
+          qi[k] = cand[k] ? yy * TW + xx : 0;
+          const int a = G::at(qi[k] / TW, qi[k] % TW);
+          jq[k] = (int)s.J[a];
+          iq[k] = (int)s.I[a];
+        }
+        uint32_t old[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+          cand[k] = cand[k] && jq[k] < jp && jq[k] < iq[k];
+          old[k] = atomicOr(&s.claim[qi[k] >> 5], cand[k] ? 1u << (qi[k] & 31) : 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+          const bool win = cand[k] && !(old[k] & (1u << (qi[k] & 31)));
+          push(s, 1, nn, win, qi[k]);
         }
       }
       wsync();
@@ -628,9 +677,11 @@ __device__ __forceinline__ void add64(uint64_t* p, uint64_t v) {
 }
 
 // Per-worker totals, flushed once when the worker exits.
+// 32-bit counts are enough for one worker within one launch (the wall clock
+// runs at 100 MHz, 43 s before a per-worker timer wraps).
 struct WorkerStats {
-  uint64_t pushes = 0, rounds = 0, iters = 0, ovf = 0, visits = 0, reproc = 0, requeued = 0;
-  uint64_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0, t_sync = 0;
+  uint32_t pushes = 0, rounds = 0, iters = 0, ovf = 0, visits = 0, reproc = 0, requeued = 0;
+  uint32_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0, t_sync = 0;
   __device__ void add(const VisitStats& v) {
     pushes += v.pushes;
     rounds += v.rounds;
@@ -734,14 +785,12 @@ __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, int gri
   }
 }
 
-// Take a tile id from queue q, or -1 when the launch is over.  Waits use
-// relaxed loads only: an acquire on gfx950 invalidates the L2 of the XCD,
-// which a waiting worker must not do to the tiles others are working on.
-// The one acquire is the exchange on the tile's state word.
-__device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                         int grid) {
-  if (ld_rlx_u32(&ctl->done.v)) return -1;
-  const uint32_t h = atomicAdd(&ctl->head[q].v, 1u);
+// Turn ticket h of queue q into a tile id, or -1 when the launch is over.
+// Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
+// the XCD, which a waiting worker must not do to the tiles others are
+// working on.  The one acquire is the exchange on the tile's state word.
+__device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
+                              int grid, uint32_t h) {
   const int64_t len = first_pass_len(kp, q);
   int v;
   if ((int64_t)h < len) {
@@ -775,13 +824,36 @@ __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* s
   return v;
 }
 
+constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
+
+// Take a tile id from queue q (using an already taken ticket if `pre` holds
+// one), or -1 when the launch is over.
+__device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
+                         int grid, uint32_t pre) {
+  if (pre == kNoTicket) {
+    if (ld_rlx_u32(&ctl->done.v)) return -1;
+    pre = atomicAdd(&ctl->head[q].v, 1u);
+  }
+  return resolve_ticket(ctl, queue, kp, state, q, grid, pre);
+}
+
+// While queue q's first pass lasts, the next ticket is taken before the
+// current tile is solved, so its round trip overlaps useful work (a first-
+// pass ticket maps to a tile without waiting).
+__device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q) {
+  if (ld_rlx_u32(&ctl->done.v)) return kNoTicket;
+  if ((int64_t)ld_rlx_u32(&ctl->head[q].v) >= first_pass_len(kp, q)) return kNoTicket;
+  return atomicAdd(&ctl->head[q].v, 1u);
+}
+
 // Publish the end of a visit of tile t (whole wavefront, after an
-// agent-scope release fence that follows the tile's write-back): ask the
-// neighbours in `act` for a visit (lane d handles neighbour d, so the nine
-// state updates share one round trip), release t, keep the pending count and
-// queue the neighbours that were idle.  Returns 1 if t must be run again (a
-// neighbour asked while it ran), 2 if this visit completed the launch, 0
-// otherwise.
+// agent-scope release fence that follows the tile's write-back).  Lanes 0..8
+// ask the neighbours in `act` for a visit while lane 9 tries to release t
+// (one round trip); then the pending count and the queue reservations of the
+// neighbours that were idle go out together (a second round trip), and only
+// after both have landed are the queue slots filled, so a queued tile is
+// always already counted.  Returns 1 if t must be run again (a neighbour
+// asked while it ran), 2 if this visit completed the launch, 0 otherwise.
 __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
                        const DevImage& im, int64_t ty, int64_t tx, uint32_t act,
                        WorkerStats& ws) {
@@ -793,34 +865,44 @@ __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* sta
       n = (int)(im.tile_base + ny * im.tiles_x + nx);
   }
   bool fresh = false;  // was idle: this wavefront enqueues it
+  bool released = false;
   if (n >= 0)
     fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT) == 0u;
-  const int nfresh = __popcll(__ballot(fresh));
-  int res = 0;
-  if (d == 0) {
+  if (d == 9) {
     uint32_t expect = TS_RUNNING;
-    const bool released = __hip_atomic_compare_exchange_strong(
+    released = __hip_atomic_compare_exchange_strong(
         &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // count the new tiles before they become visible; the running tile keeps
-    // the count above zero until this update
-    const int delta = nfresh - (released ? 1 : 0);
-    if (delta != 0) {
-      const int old = atomicAdd((int*)&ctl->pending.v, delta);
-      if (old + delta == 0) res = 2;
-    }
-    if (!released) {
-      // running | pending: take the request (acquire: the neighbour's new
-      // border becomes visible) and run again
-      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      ws.reproc++;
-      ws.visits++;
-      res = 1;
-    }
   }
-  res = __builtin_amdgcn_readfirstlane(res);
-  if (fresh) queue_push(ctl, queue, kp, n);
+  const int nfresh = __popcll(__ballot(fresh));
+  const bool rel = __ballot(released) != 0;
+  // count the new tiles and reserve their queue positions
+  const int delta = nfresh - (rel ? 1 : 0);
+  int last = 0;
+  if (d == 0 && delta != 0) {
+    const int old = atomicAdd((int*)&ctl->pending.v, delta);
+    last = old + delta == 0;
+  }
+  uint32_t pos = 0;
+  int q = 0;
+  if (fresh) {
+    q = queue_of(kp, n);
+    pos = atomicAdd(&ctl->tail[q].v, 1u);
+  }
+  int res = __builtin_amdgcn_readfirstlane(last) ? 2 : 0;
+  if (fresh)
+    __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   ws.requeued += nfresh;
+  if (!rel) {
+    // running | pending: take the request (acquire: the neighbour's new
+    // border becomes visible) and run again
+    if (d == 0)
+      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    ws.reproc++;
+    ws.visits++;
+    res = 1;
+  }
   return res;
 }
 
@@ -834,12 +916,16 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
   const int q = blockIdx.x % kp.nq;
   const int grid = gridDim.x;
   WorkerStats ws;
+  uint32_t pre = kNoTicket;  // lane 0: a ticket taken ahead of time
   for (;;) {
-    uint64_t c0 = now();
+    uint32_t c0 = (uint32_t)now();
     int t = 0;
-    if (lead) t = queue_pop(ctl, queue, kp, state, q, grid);
+    if (lead) {
+      t = queue_pop(ctl, queue, kp, state, q, grid, pre);
+      pre = kNoTicket;
+    }
     t = __builtin_amdgcn_readfirstlane(t);
-    uint64_t c1 = now();
+    uint32_t c1 = (uint32_t)now();
     ws.t_idle += c1 - c0;
     if (t < 0) break;
     ws.visits++;
@@ -852,37 +938,38 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
     VisitStats vs;
     bool hit = false;
     const bool viol = TP::load(s, im, y0, x0, first);
-    uint64_t c2 = now();
+    uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
+    if (lead) pre = prefetch_ticket(ctl, kp, q);
     TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.spin_limit, vs, hit);
-    uint64_t c3 = now();
+    uint32_t c3 = (uint32_t)now();
     ws.t_solve += c3 - c2;
     for (;;) {
       TP::store(s, im, y0, x0);
       const uint32_t act = TP::activation_mask(s);
-      uint64_t c3b = now();
+      uint32_t c3b = (uint32_t)now();
       ws.t_store += c3b - c3;
+      ws.add(vs);
       if (lead) {
         if (first) visited[t] = 1;
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
-        ws.add(vs);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
       // publish the tile before anyone is told about it
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
       if (res == 2) stop_all(ctl, queue, kp, grid);
-      uint64_t c4 = now();
+      uint32_t c4 = (uint32_t)now();
       ws.t_sync += c4 - c3b;
       if (res != 1) break;
       // a neighbour changed while this tile ran: reload the halo, continue
       vs = VisitStats();
       hit = false;
       TP::reload_halo(s, im, y0, x0);
-      uint64_t c5 = now();
+      uint32_t c5 = (uint32_t)now();
       ws.t_load += c5 - c4;
       TP::solve(s, kp.sweeps, true, kp.seed_queue_max, kp.spin_limit, vs, hit);
-      c3 = now();
+      c3 = (uint32_t)now();
       ws.t_solve += c3 - c5;
     }
   }
