@@ -142,7 +142,7 @@ def bench_single(args, torch, iwpp):
     Jt = torch.empty_like(Jt0)
     stream = torch.cuda.Stream()
     params = {"timing": 1}
-    for k in ("tile_h", "sweeps", "mode", "seed_queue"):
+    for k in ("tile_h", "sweeps", "mode", "seed_queue", "queue_waves"):
         v = getattr(args, k)
         if v is not None:
             params[k] = v
@@ -384,6 +384,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--mode", type=int, default=None)
     ap.add_argument("--seed-queue", dest="seed_queue", type=int, default=None)
+    ap.add_argument("--queue-waves", dest="queue_waves", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="c5 seconds of arrivals")

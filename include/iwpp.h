@@ -114,6 +114,9 @@ typedef struct iwpp_stats {
  *   seed_queue    a re-visited tile whose new halo can raise at most this
  *                 many border pixels goes straight to its queue; more start
  *                 with a scan round (0 = default 32, -1 = always scan).
+ *   queue_waves   a tile queue that still holds receivers after this many
+ *                 waves hands the tile to rounds of directional passes and a
+ *                 new scan (0 = default 4, -1 = no limit).
  */
 typedef struct iwpp_params {
   int32_t tile_h;
@@ -125,6 +128,7 @@ typedef struct iwpp_params {
   uint32_t spin_limit; /* bound on device-side waits (0 = default) */
   int32_t timing;
   int32_t seed_queue;
+  int32_t queue_waves;
 } iwpp_params;
 
 /* Library version, e.g. 10000 for 1.0.0. */
@@ -188,6 +192,9 @@ int iwpp_batch_destroy(iwpp_batch *b);
 /*
  * Times candidate parameter sets on one image and returns the fastest in
  * *best (bit-exactness of every candidate is the caller's to test).  The
+ * search is coordinate descent: tile height x sweeps, then seed_queue, then
+ * queue_waves, each stage from the best set so far (about 15 candidates,
+ * four runs each).  The
  * marker is left unchanged: candidates run on a scratch copy.  Results are
  * remembered per (dtype, conn, size class) and used when params are NULL;
  * if IWPP_TUNE_CACHE names a file, they are also stored there as JSON.

@@ -56,17 +56,22 @@ void load_tune_cache_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  // one JSON object per line: {"dtype":0,"conn":8,"cls":24,"tile_h":64,"sweeps":2,"mode":0}
+  // one JSON object per line: {"dtype":0,"conn":8,"cls":24,"tile_h":64,"sweeps":2,"mode":0,
+  // "seed_queue":32,"queue_waves":16} (the last two may be absent)
   char line[512];
   while (std::fgets(line, sizeof line, f)) {
-    int dt, cn, cls, th, sw, md;
-    if (std::sscanf(line,
-                    " {\"dtype\":%d,\"conn\":%d,\"cls\":%d,\"tile_h\":%d,\"sweeps\":%d,\"mode\":%d",
-                    &dt, &cn, &cls, &th, &sw, &md) == 6) {
+    int dt, cn, cls, th, sw, md, sq = 0, qw = 0;
+    const int got = std::sscanf(line,
+                                " {\"dtype\":%d,\"conn\":%d,\"cls\":%d,\"tile_h\":%d,\"sweeps\":%d,"
+                                "\"mode\":%d,\"seed_queue\":%d,\"queue_waves\":%d",
+                                &dt, &cn, &cls, &th, &sw, &md, &sq, &qw);
+    if (got == 6 || got == 8) {
       iwpp_params p{};
       p.tile_h = th;
       p.sweeps = sw;
       p.mode = md;
+      p.seed_queue = sq;
+      p.queue_waves = qw;
       g_tuned[{dt, cn, cls}] = p;
     }
   }
@@ -80,9 +85,12 @@ void save_tune_cache_locked() {
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return;
   for (auto& kv : g_tuned) {
-    std::fprintf(f, "{\"dtype\":%d,\"conn\":%d,\"cls\":%d,\"tile_h\":%d,\"sweeps\":%d,\"mode\":%d}\n",
+    std::fprintf(f,
+                 "{\"dtype\":%d,\"conn\":%d,\"cls\":%d,\"tile_h\":%d,\"sweeps\":%d,\"mode\":%d,"
+                 "\"seed_queue\":%d,\"queue_waves\":%d}\n",
                  std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                 kv.second.tile_h, kv.second.sweeps, kv.second.mode);
+                 kv.second.tile_h, kv.second.sweeps, kv.second.mode, kv.second.seed_queue,
+                 kv.second.queue_waves);
   }
   std::fclose(f);
   std::rename(tmp.c_str(), path);
@@ -92,15 +100,17 @@ void save_tune_cache_locked() {
 
 namespace iwpp {
 
-int default_tile_h(int dtype) { return dtype == IWPP_U8 ? 64 : 64; }
+int default_tile_h(int dtype) { return dtype == IWPP_U8 ? 64 : 32; }
 
 // Resolve user params (NULL / zero fields) against tuned and default values.
 Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W) {
   Resolved r{};
   iwpp_params base{};
   base.tile_h = default_tile_h(dtype);
-  base.sweeps = 2;
+  base.sweeps = dtype == IWPP_U8 ? 2 : 1;
   base.mode = 0;
+  base.seed_queue = 32;
+  base.queue_waves = 4;
   {
     std::lock_guard<std::mutex> g(g_mu);
     load_tune_cache_locked();
@@ -109,6 +119,8 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
       if (it->second.tile_h) base.tile_h = it->second.tile_h;
       if (it->second.sweeps) base.sweeps = it->second.sweeps < 0 ? 0 : it->second.sweeps;
       base.mode = it->second.mode;
+      if (it->second.seed_queue) base.seed_queue = it->second.seed_queue;
+      if (it->second.queue_waves) base.queue_waves = it->second.queue_waves;
     }
   }
   r.tile_h = base.tile_h;
@@ -119,10 +131,13 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   r.order_seed = 0;
   r.spin_limit = 1u << 24;
   r.timing = 0;
-  r.seed_queue_max = 32;
+  r.seed_queue_max = base.seed_queue < 0 ? 0 : base.seed_queue;
+  r.queue_waves = base.queue_waves < 0 ? UINT32_MAX : (uint32_t)base.queue_waves;
   if (user) {
     r.timing = user->timing;
     if (user->seed_queue) r.seed_queue_max = user->seed_queue < 0 ? 0 : user->seed_queue;
+    if (user->queue_waves)
+      r.queue_waves = user->queue_waves < 0 ? UINT32_MAX : (uint32_t)user->queue_waves;
     if (user->tile_h) r.tile_h = user->tile_h;
     if (user->sweeps) r.sweeps = user->sweeps < 0 ? 0 : user->sweeps;
     if (user->mode) r.mode = user->mode;
@@ -333,6 +348,7 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
   kp.max_visits = rp.max_visits;
   kp.spin_limit = rp.spin_limit;
   kp.seed_queue_max = rp.seed_queue_max;
+  kp.queue_waves = rp.queue_waves;
   int64_t nl = 0;
   if (rp.mode == 0) {
     int grid = 0;
@@ -765,38 +781,58 @@ int iwpp_autotune(const iwpp_image* img, int dtype, int conn, iwpp_stream_t stre
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  std::vector<int> tiles = dtype == IWPP_U8 ? std::vector<int>{64, 128} : std::vector<int>{64};
-  const int sweeps[] = {-1, 1, 2, 4};
+  // median of three timed runs (after one warm-up) from the pristine marker
+  auto time_of = [&](const iwpp_params& p, float* out) -> int {
+    iwpp_image im = *img;
+    im.marker = scratch;
+    std::vector<float> times;
+    for (int rep = 0; rep < 4; ++rep) {
+      (void)hipMemcpyAsync(scratch, img->marker, bytes, hipMemcpyDeviceToDevice, st);
+      (void)hipEventRecord(e0, st);
+      int r = iwpp_reconstruct_async(&im, dtype, conn, IWPP_FLAG_CLAMP_MARKER, &p, stream);
+      (void)hipEventRecord(e1, st);
+      const int s2 = iwpp_stream_status(stream, nullptr);
+      if (!r && s2 != IWPP_OK) r = s2;
+      if (r) return r;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep) times.push_back(ms);
+    }
+    std::sort(times.begin(), times.end());
+    *out = times[times.size() / 2];
+    return IWPP_OK;
+  };
+  // coordinate descent: tile height x sweeps, then the seeded-queue bound,
+  // then the queue-wave bound, each stage starting from the best so far
+  const std::vector<int> tiles =
+      dtype == IWPP_U8 ? std::vector<int>{64, 128} : std::vector<int>{32, 64};
   float best_ms = 1e30f;
   iwpp_params bp{};
-  for (int th : tiles) {
-    for (int sw : sweeps) {
+  auto consider = [&](const iwpp_params& p) -> int {
+    float ms = 0;
+    const int r = time_of(p, &ms);
+    if (!r && ms < best_ms) {
+      best_ms = ms;
+      bp = p;
+    }
+    return r;
+  };
+  for (int th : tiles)
+    for (int sw : {1, 2, 4, -1}) {
       iwpp_params p{};
       p.tile_h = th;
       p.sweeps = sw;
-      iwpp_image im = *img;
-      im.marker = scratch;
-      std::vector<float> times;
-      for (int rep = 0; rep < 4 && !rc; ++rep) {
-        (void)hipMemcpyAsync(scratch, img->marker, bytes, hipMemcpyDeviceToDevice, st);
-        (void)hipEventRecord(e0, st);
-        rc = iwpp_reconstruct_async(&im, dtype, conn, IWPP_FLAG_CLAMP_MARKER, &p, stream);
-        (void)hipEventRecord(e1, st);
-        int s2 = iwpp_stream_status(stream, nullptr);
-        if (!rc && s2 != IWPP_OK) rc = s2;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep) times.push_back(ms);  // first run warms up
-      }
-      if (rc) break;
-      std::sort(times.begin(), times.end());
-      const float med = times[times.size() / 2];
-      if (med < best_ms) {
-        best_ms = med;
-        bp = p;
-      }
+      if (!rc) rc = consider(p);
     }
-    if (rc) break;
+  for (int sq : {8, 32, -1}) {
+    iwpp_params p = bp;
+    p.seed_queue = sq;
+    if (!rc) rc = consider(p);
+  }
+  for (int qw : {4, 16, 64, -1}) {
+    iwpp_params p = bp;
+    p.queue_waves = qw;
+    if (!rc) rc = consider(p);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

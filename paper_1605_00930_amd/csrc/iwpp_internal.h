@@ -69,6 +69,7 @@ struct KParams {
   uint32_t spin_limit;  // bounded waits (iterations)
   int32_t first_round;  // host-driven rounds: this is the first round
   int32_t seed_queue_max;  // re-visits with at most this many halo receivers skip the scans
+  uint32_t queue_waves;    // queue waves before a tile falls back to sweep rounds
   int32_t nq;           // tile queues in use (1..kMaxQueues)
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles

@@ -59,6 +59,32 @@ __device__ __forceinline__ int32_t ld_rlx_i32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Marker pixels cross workgroups that may sit on different XCDs, each with
+// its own L2.  They are only ever read and written with agent-scope relaxed
+// atomic accesses: on gfx950 such a load is served coherently for the whole
+// device and such a store writes through, so no L2 write-back or invalidate
+// (what an agent-scope fence costs) is needed to hand a tile from one
+// workgroup to another.  Ordering comes from drain_memory() below.
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coherent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every memory access this wavefront has issued is complete (an
+// agent-scope store is then visible to the whole device), and keep the
+// compiler from moving memory accesses across the wait.  Used after the
+// marker write-back, before the tile is published, and after a tile is
+// taken, before its marker is read.
+__device__ __forceinline__ void drain_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Lane i receives v from lane i-1; lane 0 receives `fill`.
 __device__ __forceinline__ int from_left(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
@@ -180,7 +206,7 @@ struct Tile {
         const int64_t gy = gy0 + k;
         j[k] = i[k] = LO;
         if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
-          j[k] = (int)pj[k * im.ld];
+          j[k] = (int)ld_coherent(&pj[k * im.ld]);
           i[k] = (int)pi[k * im.ld];
         }
       }
@@ -192,7 +218,7 @@ struct Tile {
           const int64_t ey = y0 + yy - 1, ex = x0 + c - 1;
           ej[k] = ei[k] = LO;
           if (e < NE && ey >= 0 && ey < im.H && ex < im.W) {
-            ej[k] = (int)gJ[ey * im.ld + ex];
+            ej[k] = (int)ld_coherent(&gJ[ey * im.ld + ex]);
             ei[k] = (int)gI[ey * im.ld + ex];
           }
         }
@@ -269,7 +295,7 @@ struct Tile {
       const int64_t gy = y0 + y, gx = x0 + x;
       if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
         const int i = iv(s, y, x);
-        const int j = (int)gJ[gy * im.ld + gx];
+        const int j = (int)ld_coherent(&gJ[gy * im.ld + gx]);
         s.J[G::at(y, x)] = (T)imin(j, i);
       }
     }
@@ -277,9 +303,6 @@ struct Tile {
     snapshot_border(s);
     wsync();
   }
-
-  // Write one marker pixel back to memory.
-  __device__ static void put(T* p, T v) { *p = v; }
 
   __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0) {
     T* __restrict__ gJ = (T*)im.J;
@@ -292,7 +315,7 @@ struct Tile {
         const int y = g + __builtin_ctzll(rows);
         rows &= rows - 1;
         const int64_t gy = y0 + y;
-        if (gy < im.H && col_in) put(&gJ[gy * im.ld + gx], s.J[G::at(y, lane())]);
+        if (gy < im.H && col_in) st_coherent(&gJ[gy * im.ld + gx], s.J[G::at(y, lane())]);
       }
     }
   }
@@ -504,9 +527,11 @@ struct Tile {
   // ---------------------------------------------------------- queue phase
   // Two-phase queue loop starting from n receivers in queue 0.  Returns
   // false when the queue ran dry (the tile is at a fixed point), true on
-  // overflow (then a scan round must follow).
-  __device__ static bool queue_loop(L& s, int n, VisitStats& vs, uint32_t iter_limit,
-                                    bool& hit_limit) {
+  // overflow or after `waves` waves with receivers left (then sweep rounds
+  // and a scan must follow: a front that winds through the tile is carried
+  // further by one round of passes than by many queue waves).
+  __device__ static bool queue_loop(L& s, int n, VisitStats& vs, uint32_t waves,
+                                    uint32_t iter_limit, bool& hit_limit) {
     for (int w = lane(); w < G::NWORDS; w += 64) s.claim[w] = 0;
     wsync();
     for (uint32_t iter = 0;; ++iter) {
@@ -515,6 +540,7 @@ struct Tile {
         return true;
       }
       if (n == 0) return false;
+      if (iter >= waves) return true;
       if (iter >= iter_limit) {
         hit_limit = true;
         return false;
@@ -590,13 +616,14 @@ struct Tile {
   // tile was at a fixed point for an older halo, so only border pixels next
   // to a changed halo pixel can rise at first.
   __device__ static void solve(L& s, int sweeps, bool seeded, int seed_queue_max,
-                               uint32_t iter_limit, VisitStats& vs, bool& hit_limit) {
+                               uint32_t waves, uint32_t iter_limit, VisitStats& vs,
+                               bool& hit_limit) {
     int budget = sweeps;
     if (seeded) {
       const int n = halo_receivers(s);
       if (n == 0) return;
       if (n <= seed_queue_max) {
-        if (!queue_loop(s, n, vs, iter_limit, hit_limit)) return;
+        if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
       }
       if (budget < 1) budget = 1;
     }
@@ -609,7 +636,7 @@ struct Tile {
       if (!ch) return;  // a round that changed nothing: fixed point
       const int n = scan_receivers(s);
       if (n == 0) return;
-      if (!queue_loop(s, n, vs, iter_limit, hit_limit)) return;
+      if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
       if (budget < 1) budget = 1;
       if (guard >= iter_limit) {
         hit_limit = true;
@@ -788,7 +815,7 @@ __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, int gri
 // Turn ticket h of queue q into a tile id, or -1 when the launch is over.
 // Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
 // the XCD, which a waiting worker must not do to the tiles others are
-// working on.  The one acquire is the exchange on the tile's state word.
+// working on.
 __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
                               int grid, uint32_t h) {
   const int64_t len = first_pass_len(kp, q);
@@ -819,8 +846,11 @@ __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32
       return -1;
     }
   }
-  // pending -> running; the acquire makes the tile and its halo visible
-  __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  // pending -> running.  A neighbour that asked for this visit finished its
+  // marker stores before its request reached the state word, so once the
+  // exchange is complete, the marker reads that follow see them.
+  __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  drain_memory();
   return v;
 }
 
@@ -846,8 +876,8 @@ __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q) {
   return atomicAdd(&ctl->head[q].v, 1u);
 }
 
-// Publish the end of a visit of tile t (whole wavefront, after an
-// agent-scope release fence that follows the tile's write-back).  Lanes 0..8
+// Publish the end of a visit of tile t (whole wavefront, once the tile's
+// marker write-back is complete).  Lanes 0..8
 // ask the neighbours in `act` for a visit while lane 9 tries to release t
 // (one round trip); then the pending count and the queue reservations of the
 // neighbours that were idle go out together (a second round trip), and only
@@ -895,10 +925,12 @@ __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* sta
                        __HIP_MEMORY_SCOPE_AGENT);
   ws.requeued += nfresh;
   if (!rel) {
-    // running | pending: take the request (acquire: the neighbour's new
-    // border becomes visible) and run again
+    // running | pending: take the request and run again (the failed release
+    // already saw the request, so the halo reads that follow see the
+    // neighbour's new border)
     if (d == 0)
-      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    drain_memory();
     ws.reproc++;
     ws.visits++;
     res = 1;
@@ -934,14 +966,15 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
     const int64_t tl = (int64_t)t - im.tile_base;
     const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
     const int64_t y0 = ty * TH, x0 = tx * TW;
-    const bool first = visited[t] == 0;
+    const bool first = ld_coherent(&visited[t]) == 0;
     VisitStats vs;
     bool hit = false;
     const bool viol = TP::load(s, im, y0, x0, first);
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
     if (lead) pre = prefetch_ticket(ctl, kp, q);
-    TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.spin_limit, vs, hit);
+    TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit, vs,
+                hit);
     uint32_t c3 = (uint32_t)now();
     ws.t_solve += c3 - c2;
     for (;;) {
@@ -951,12 +984,12 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
       ws.t_store += c3b - c3;
       ws.add(vs);
       if (lead) {
-        if (first) visited[t] = 1;
+        if (first) st_coherent(&visited[t], (uint8_t)1);
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
-      // publish the tile before anyone is told about it
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // the write-back is complete before anyone is told about it
+      drain_memory();
       const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
       if (res == 2) stop_all(ctl, queue, kp, grid);
       uint32_t c4 = (uint32_t)now();
@@ -968,7 +1001,8 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
       TP::reload_halo(s, im, y0, x0);
       uint32_t c5 = (uint32_t)now();
       ws.t_load += c5 - c4;
-      TP::solve(s, kp.sweeps, true, kp.seed_queue_max, kp.spin_limit, vs, hit);
+      TP::solve(s, kp.sweeps, true, kp.seed_queue_max, kp.queue_waves, kp.spin_limit, vs,
+                hit);
       c3 = (uint32_t)now();
       ws.t_solve += c3 - c5;
     }
@@ -1000,7 +1034,8 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   VisitStats vs;
   bool hit = false;
   const bool viol = TP::load(s, im, y0, x0, first);
-  TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.spin_limit, vs, hit);
+  TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit, vs,
+                hit);
   TP::store(s, im, y0, x0);
   const uint32_t act = TP::activation_mask(s);
   if (threadIdx.x == 0) {

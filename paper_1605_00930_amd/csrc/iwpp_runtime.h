@@ -21,6 +21,7 @@ struct Resolved {
   uint32_t spin_limit;
   int timing;
   int seed_queue_max;
+  uint32_t queue_waves;
 };
 
 // Device buffers of one launch context (a stream workspace, a batch plan or a

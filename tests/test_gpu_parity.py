@@ -124,7 +124,8 @@ def test_row_pitch(iwpp):
     {"mode": 1}, {"sweeps": -1}, {"sweeps": 1}, {"sweeps": 4}, {"tile_h": 128},
     {"tile_h": 32}, {"order_seed": 7}, {"order_seed": 12345, "sweeps": -1}, {"grid": 3},
     {"grid": 1}, {"mode": 1, "sweeps": -1}, {"mode": 1, "tile_h": 128}, {"seed_queue": -1},
-    {"seed_queue": 100000}, {"seed_queue": 100000, "sweeps": -1},
+    {"seed_queue": 100000}, {"seed_queue": 100000, "sweeps": -1}, {"queue_waves": 1},
+    {"queue_waves": -1}, {"queue_waves": 2, "seed_queue": 100000, "sweeps": -1},
 ])
 def test_parameters_do_not_change_the_result(iwpp, params):
     th = params.get("tile_h")
