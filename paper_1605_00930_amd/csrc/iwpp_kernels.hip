@@ -124,7 +124,9 @@ struct Geo {
   static constexpr int P = sizeof(T) == 1 ? TW + 4 : TW + 3;
   static constexpr int ROWS = TH + 2;
   static constexpr int NPIX = TH * TW;
-  static constexpr int QCAP = sizeof(T) == 1 ? NPIX : NPIX / 2;
+  // Queue capacity: a fraction of the tile, so that eight tiles fit in a
+  // CU's LDS; an overflowing queue falls back to rounds of passes.
+  static constexpr int QCAP = sizeof(T) == 1 ? NPIX / 4 : NPIX / 8;
   static constexpr int NWORDS = NPIX / 32;
   static constexpr int RING = 2 * TW + 2 * (TH - 2);  // border pixels, each once
   static constexpr int HALO = 2 * (TW + 2) + 2 * TH;  // halo pixels
