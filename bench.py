@@ -17,6 +17,13 @@ Workloads (--workload):
   c5     served stream: Poisson arrivals at 2000 req/s into the
          continuous-batching server
 
+Operation (--op, single-image workloads):
+  dilate  reconstruction by dilation of the workload (default)
+  erode   reconstruction by erosion of the dual workload: mask and marker
+          complemented (255 - x / -1 - x), so the marker lies above the mask
+  fill    fill holes of the workload's mask (frame-marker kernel plus the
+          reconstruction by erosion, both inside the timed region)
+
 Extras in the JSON line:
   roofline      for the dominant kernel (the persistent tile kernel):
                 algorithmic bytes 3*sizeof(T) per pixel per launch over its
@@ -92,7 +99,7 @@ def make_workload(name: str, scale: int = 1):
     raise ValueError(name)
 
 
-def cpu_baseline(name: str, budget_s: float = 20.0):
+def cpu_baseline(name: str, budget_s: float = 20.0, op: str = "dilate"):
     """Time the oracle (single thread) on a bounded sample of the workload."""
     import oracle
     import synth
@@ -119,8 +126,15 @@ def cpu_baseline(name: str, budget_s: float = 20.0):
     runs = 0
     while t < budget_s and runs < 10:
         for I, J in pairs:
+            if op == "erode":
+                J, I = np.invert(J), np.invert(I)
             t0 = time.perf_counter()
-            rc, _ = oracle.reconstruct(J, I, 8)
+            if op == "fill":
+                rc, _ = oracle.fill_holes(I, 8)
+            elif op == "erode":
+                rc, _ = oracle.reconstruct_erode(J, I, 8)
+            else:
+                rc, _ = oracle.reconstruct(J, I, 8)
             t += time.perf_counter() - t0
             assert rc == 0
             px += I.size
@@ -135,6 +149,8 @@ def bench_single(args, torch, iwpp):
     pairs, dt, desc = make_workload(args.workload, args.scale)
     log("generated %s in %.1f s" % (args.workload, time.perf_counter() - t0))
     (I, J), = pairs
+    if args.op == "erode":
+        I, J = np.invert(I), np.invert(J)
     H, W = I.shape
     Jt0 = torch.from_numpy(J).to(dev)
     It = torch.from_numpy(I).to(dev)
@@ -155,10 +171,16 @@ def bench_single(args, torch, iwpp):
             torch.cuda.synchronize()
             t_wall0 = time.perf_counter()
         with torch.cuda.stream(stream):
-            Jt.copy_(Jt0)
-            ev0.record(stream)
-            iwpp.reconstruct_async(Jt, It, 8, params=params, stream=stream)
-            ev1.record(stream)
+            if args.op == "fill":
+                ev0.record(stream)
+                iwpp.fill_holes(It, Jt, 8, params=params, stream=stream, check=False)
+                ev1.record(stream)
+            else:
+                Jt.copy_(Jt0)
+                ev0.record(stream)
+                iwpp.reconstruct_async(Jt, It, 8, params=params, stream=stream,
+                                       erosion=args.op == "erode")
+                ev1.record(stream)
         st = iwpp.stream_status(stream)
         log("step %d: %.3f ms (kernel %.3f ms, visits %d)"
             % (step, ev0.elapsed_time(ev1), st["kernel_ms"], st["tile_visits"]))
@@ -173,13 +195,14 @@ def bench_single(args, torch, iwpp):
     kms = float(np.mean(kern_ms))
     px = H * W
     achieved = 3 * es * px / (kms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload)
+    traffic = load_traffic(args.workload) if args.op == "dilate" else None
     res = {
         "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic",
-        "config": {"workload": args.workload, "desc": desc, "H": H, "W": W, "conn": 8,
+        "config": {"workload": args.workload, "op": args.op, "desc": desc, "H": H, "W": W,
+                   "conn": 8,
                    "params": {k: v for k, v in params.items() if k != "timing"}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -380,6 +403,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3u8", "c3i32", "c4", "c5"])
     ap.add_argument("--scale", type=int, default=1, help="divide the 32K side (c3*) by this")
+    ap.add_argument("--op", default="dilate", choices=["dilate", "erode", "fill"],
+                    help="single-image workloads: which operation to time")
     ap.add_argument("--tile-h", dest="tile_h", type=int, default=None)
     ap.add_argument("--sweeps", type=int, default=None)
     ap.add_argument("--mode", type=int, default=None)
@@ -396,6 +421,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run the library copy kernel on this many MiB (profiler scaling)")
     args = ap.parse_args()
+    if args.op != "dilate" and args.workload in ("c4", "c5"):
+        ap.error("--op applies to single-image workloads only")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -431,7 +458,7 @@ def main():
     else:
         res = bench_single(args, torch, iwpp)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.op)
     res["kernel_source_sha256"] = kernel_source_hash()
     print(json.dumps(res), flush=True)
 

@@ -28,6 +28,15 @@
  *  - If J > I at some pixel the call reports IWPP_E_MARKER_GT_MASK; the
  *    marker then holds R_I(min(J, I)).  With IWPP_FLAG_CLAMP_MARKER the same
  *    result is produced and the call succeeds.
+ *  - With IWPP_FLAG_EROSION the call computes the reconstruction by erosion
+ *    instead (the "max/min" choice of the IWPP algorithm): J >= I, and J
+ *    becomes the limit of J <- erode_G(J) v I (v the pixelwise maximum).  It
+ *    runs the same kernels through duality: tiles hold the bitwise
+ *    complement (255 - x for uint8, -1 - x for int32, both order-reversing),
+ *    applied as values are staged and written back, so it moves no extra
+ *    bytes.  Its precondition error is J < I somewhere (reported as
+ *    IWPP_E_MARKER_GT_MASK of the complemented images); with
+ *    IWPP_FLAG_CLAMP_MARKER the marker is max(J, I).
  *  - The library keeps a workspace per (device, stream), grown on demand and
  *    freed by iwpp_release_workspace().  Calls on one stream run in stream
  *    order; calls on different streams may run concurrently.
@@ -62,6 +71,7 @@ extern "C" {
 
 /* ---- flags ---- */
 #define IWPP_FLAG_CLAMP_MARKER 1u /* use min(J, I) as the marker, no error */
+#define IWPP_FLAG_EROSION 2u      /* reconstruction by erosion (see above)    */
 
 typedef void *iwpp_stream_t;
 
@@ -234,6 +244,23 @@ int iwpp_server_destroy(iwpp_server *s);
 
 /* Frees the cached per-stream workspaces (after synchronising the device). */
 int iwpp_release_workspace(void);
+
+/*
+ * Fill holes ("Fill Holes" subsection of the IWPP chapter): `out` receives
+ * the image with every hole filled, where a hole is a region the image's
+ * 1-pixel frame cannot reach without climbing; a grayscale hole is raised to
+ * the lowest level through which it can be left.  Computed as the
+ * reconstruction by erosion of `image` from a marker equal to the image on
+ * its frame and the highest value inside (equivalently, by duality, the
+ * complement of the reconstruction by dilation of the complemented image
+ * from its frame).  `image` (in) and `out` (out) are device arrays of H x W
+ * pixels with row pitch `ld` (0 = W) that must not overlap.  Asynchronous
+ * on `stream` like iwpp_reconstruct_async: one marker-initialisation kernel,
+ * then the reconstruction; iwpp_stream_status() reports the result.
+ */
+int iwpp_fill_holes_async(const void *image, void *out, int64_t H, int64_t W, int64_t ld,
+                          int dtype, int conn, const iwpp_params *params,
+                          iwpp_stream_t stream);
 
 /*
  * Plain device-to-device streaming copy of `bytes` (a multiple of 16) with

@@ -17,6 +17,11 @@ arrays through ctypes.
   (the priority-queue ordering of "Uso de Diferentes Estruturas de Dados").
 * :func:`pixels` -- R at chosen pixels only, for sampled checks of images
   too large to reconstruct whole.
+* :func:`reconstruct_erode` -- reconstruction by erosion (the "min" choice of
+  the IWPP algorithm's max/min update), through the duality of reconstruction
+  by erosion and by dilation under an order-reversing complement.
+* :func:`fill_holes` -- the "Fill Holes" operation of the IWPP chapter: the
+  reconstruction by erosion of the image from its own 1-pixel frame.
 """
 from __future__ import annotations
 
@@ -149,3 +154,39 @@ def pixels(J: np.ndarray, I: np.ndarray, rows, cols, conn: int = 8, max_visit: i
         J.ctypes.data, I.ctypes.data, J.shape[0], J.shape[1], conn,
         rows.ctypes.data, cols.ctypes.data, rows.shape[0], max_visit, out.ctypes.data)
     return rc, out
+
+
+def complement(a: np.ndarray) -> np.ndarray:
+    """Order-reversing complement: 255 - x for uint8, -1 - x for int32 (the
+    bitwise NOT, an involution on each type's full range)."""
+    return np.invert(a)
+
+
+def reconstruct_erode(J: np.ndarray, I: np.ndarray, conn: int = 8, *, clamp: bool = False):
+    """Reconstruction by erosion of mask I from marker J >= I: the limit of
+    J <- max(erode(J), I).  Uses the duality R^eps_I(J) = C(R_C(I)(C(J))) for
+    any order-reversing bijection C, with the hybrid algorithm above for the
+    dilation.  Status E_MARKER_GT_MASK means J < I somewhere (with ``clamp``
+    the marker max(J, I) is used instead).  Returns (status, R)."""
+    rc, R = reconstruct(complement(J), complement(I), conn, clamp=clamp)
+    return rc, complement(R)
+
+
+def highest(dtype) -> int:
+    return int(np.iinfo(dtype).max)
+
+
+def fill_holes(image: np.ndarray, conn: int = 8):
+    """Fill holes: reconstruction by erosion of the image from a marker that
+    equals the image on its 1-pixel frame and the type's highest value
+    elsewhere.  Regions the frame reaches are lowered back to the image;
+    regions it cannot reach (holes) stay raised to the lowest level through
+    which they can be left.  Returns (status, filled)."""
+    if image.ndim != 2:
+        raise ValueError("fill_holes takes a 2-D image")
+    F = np.full_like(image, highest(image.dtype))
+    F[0, :] = image[0, :]
+    F[-1, :] = image[-1, :]
+    F[:, 0] = image[:, 0]
+    F[:, -1] = image[:, -1]
+    return reconstruct_erode(F, np.ascontiguousarray(image), conn)

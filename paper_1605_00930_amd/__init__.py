@@ -29,6 +29,7 @@ E_TIMEOUT = -8
 E_UNSUPPORTED = -9
 U8, I32 = 0, 1
 FLAG_CLAMP_MARKER = 1
+FLAG_EROSION = 2
 
 
 class IwppError(RuntimeError):
@@ -106,6 +107,7 @@ def _load():
         "iwpp_server_destroy": ([vp], i32),
         "iwpp_release_workspace": ([], i32),
         "iwpp_device_copy": ([vp, vp, ctypes.c_size_t, vp], i32),
+        "iwpp_fill_holes_async": ([vp, vp, i64, i64, i64, i32, i32, P(Params), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -177,12 +179,16 @@ def _ptr(p):
 # ---------------------------------------------------------------- entry points
 
 
-def reconstruct_async(marker, mask, conn: int = 8, *, clamp: bool = False, params=None,
-                      stream=None) -> None:
-    """Queue R_mask(marker) in place on `stream` (default: torch's current)."""
+def _flags(clamp: bool, erosion: bool) -> int:
+    return (FLAG_CLAMP_MARKER if clamp else 0) | (FLAG_EROSION if erosion else 0)
+
+
+def reconstruct_async(marker, mask, conn: int = 8, *, clamp: bool = False,
+                      erosion: bool = False, params=None, stream=None) -> None:
+    """Queue R_mask(marker) in place on `stream` (default: torch's current);
+    `erosion` selects the reconstruction by erosion (marker >= mask)."""
     im, dt = _image(marker, mask)
-    rc = _load().iwpp_reconstruct_async(ctypes.byref(im), dt, conn,
-                                        FLAG_CLAMP_MARKER if clamp else 0,
+    rc = _load().iwpp_reconstruct_async(ctypes.byref(im), dt, conn, _flags(clamp, erosion),
                                         _ptr(_params(params)), _stream_handle(stream))
     if rc != OK:
         raise IwppError(rc, "iwpp_reconstruct_async")
@@ -199,22 +205,45 @@ def stream_status(stream=None, *, check: bool = True) -> dict:
     return d
 
 
-def reconstruct(marker, mask, conn: int = 8, *, clamp: bool = False, params=None,
-                stream=None, check: bool = True) -> dict:
+def reconstruct(marker, mask, conn: int = 8, *, clamp: bool = False, erosion: bool = False,
+                params=None, stream=None, check: bool = True) -> dict:
     """Synchronous R_mask(marker) in place; returns the work counters."""
-    reconstruct_async(marker, mask, conn, clamp=clamp, params=params, stream=stream)
+    reconstruct_async(marker, mask, conn, clamp=clamp, erosion=erosion, params=params,
+                      stream=stream)
     return stream_status(stream, check=check)
 
 
-def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, params=None,
-                        stream=None, check: bool = True) -> dict:
+def fill_holes(image, out=None, conn: int = 8, *, params=None, stream=None,
+               check: bool = True):
+    """Fill the holes of `image` into `out` (allocated like `image` if None).
+    Returns (out, counters)."""
+    import torch
+
+    if out is None:
+        out = torch.empty_like(image)
+    if image.dim() != 2 or out.shape != image.shape or out.dtype != image.dtype:
+        raise ValueError("image and out must be 2-D tensors of one shape and dtype")
+    if not (image.is_cuda and out.is_cuda) or image.device != out.device:
+        raise ValueError("image and out must live on the same GPU")
+    if image.stride(1) != 1 or out.stride(1) != 1 or image.stride(0) != out.stride(0):
+        raise ValueError("rows must be contiguous with one common row pitch")
+    H, W = image.shape
+    rc = _load().iwpp_fill_holes_async(image.data_ptr(), out.data_ptr(), H, W, image.stride(0),
+                                       _dtype_code(image), conn, _ptr(_params(params)),
+                                       _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_fill_holes_async")
+    return out, stream_status(stream, check=check)
+
+
+def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, erosion: bool = False,
+                        params=None, stream=None, check: bool = True) -> dict:
     """Reconstruct [(marker, mask), ...] in one persistent launch."""
     ims, dts = zip(*(_image(m, k) for m, k in pairs))
     if len(set(dts)) != 1:
         raise TypeError("all images of a batch must share a dtype")
     arr = (Image * len(ims))(*ims)
-    rc = _load().iwpp_reconstruct_batched(arr, len(ims), dts[0], conn,
-                                          FLAG_CLAMP_MARKER if clamp else 0,
+    rc = _load().iwpp_reconstruct_batched(arr, len(ims), dts[0], conn, _flags(clamp, erosion),
                                           _ptr(_params(params)), _stream_handle(stream))
     if rc != OK:
         raise IwppError(rc, "iwpp_reconstruct_batched")
@@ -224,15 +253,15 @@ def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, params=Non
 class Batch:
     """A reusable batch plan (optionally replayed as a HIP graph)."""
 
-    def __init__(self, pairs, conn: int = 8, *, clamp: bool = False, params=None):
+    def __init__(self, pairs, conn: int = 8, *, clamp: bool = False, erosion: bool = False,
+                 params=None):
         ims, dts = zip(*(_image(m, k) for m, k in pairs))
         if len(set(dts)) != 1:
             raise TypeError("all images of a batch must share a dtype")
         self._keep = list(pairs)
         arr = (Image * len(ims))(*ims)
         h = ctypes.c_void_p()
-        rc = _load().iwpp_batch_create(arr, len(ims), dts[0], conn,
-                                       FLAG_CLAMP_MARKER if clamp else 0,
+        rc = _load().iwpp_batch_create(arr, len(ims), dts[0], conn, _flags(clamp, erosion),
                                        _ptr(_params(params)), ctypes.byref(h))
         if rc != OK:
             raise IwppError(rc, "iwpp_batch_create")

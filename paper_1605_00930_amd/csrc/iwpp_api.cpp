@@ -173,10 +173,12 @@ int check_image(const iwpp_image* im, int dtype) {
   return IWPP_OK;
 }
 
+uint32_t flip_of(uint32_t flags) { return (flags & IWPP_FLAG_EROSION) ? ~0u : 0u; }
+
 int check_common(int dtype, int conn, uint32_t flags) {
   if (dtype != IWPP_U8 && dtype != IWPP_I32) return IWPP_E_ARG;
   if (conn != 4 && conn != 8) return IWPP_E_ARG;
-  if (flags & ~IWPP_FLAG_CLAMP_MARKER) return IWPP_E_ARG;
+  if (flags & ~(IWPP_FLAG_CLAMP_MARKER | IWPP_FLAG_EROSION)) return IWPP_E_ARG;
   return IWPP_OK;
 }
 
@@ -349,6 +351,7 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
   kp.spin_limit = rp.spin_limit;
   kp.seed_queue_max = rp.seed_queue_max;
   kp.queue_waves = rp.queue_waves;
+  kp.flip = rp.flip;
   int64_t nl = 0;
   if (rp.mode == 0) {
     int grid = 0;
@@ -530,7 +533,8 @@ int iwpp_reconstruct_async(const iwpp_image* img, int dtype, int conn, uint32_t 
   if (!rc) rc = check_image(img, dtype);
   if (!rc) rc = check_params(params);
   if (rc) return rc;
-  const Resolved rp = resolve_params(params, dtype, conn, img->H, img->W);
+  Resolved rp = resolve_params(params, dtype, conn, img->H, img->W);
+  rp.flip = flip_of(flags);
   const Variant v{dtype, conn, rp.tile_h};
   if (!variant_supported(v)) return IWPP_E_UNSUPPORTED;
   const DevImage one = make_dev_image(*img, rp.tile_h, 0);
@@ -547,6 +551,23 @@ int iwpp_reconstruct_async(const iwpp_image* img, int dtype, int conn, uint32_t 
   rc = enqueue(w->buf, v, rp, one, nullptr, 1, ntiles, st, &w->launches);
   w->enqueue_rc = rc;
   return rc;
+}
+
+int iwpp_fill_holes_async(const void* image, void* out, int64_t H, int64_t W, int64_t ld,
+                          int dtype, int conn, const iwpp_params* params,
+                          iwpp_stream_t stream) {
+  int rc = check_common(dtype, conn, 0);
+  iwpp_image im{};
+  im.marker = out;
+  im.mask = image;
+  im.H = H;
+  im.W = W;
+  im.ld = ld;
+  if (!rc) rc = check_image(&im, dtype);
+  if (!rc) rc = check_params(params);
+  if (rc) return rc;
+  HIP_TRY(launch_frame_marker(dtype, out, image, H, W, ld ? ld : W, (hipStream_t)stream));
+  return iwpp_reconstruct_async(&im, dtype, conn, IWPP_FLAG_EROSION, params, stream);
 }
 
 int iwpp_stream_status(iwpp_stream_t stream, iwpp_stats* stats) {
@@ -580,7 +601,8 @@ int iwpp_reconstruct_batched(const iwpp_image* imgs, int32_t n, int dtype, int c
   if (rc) return rc;
   int64_t maxpx = 0;
   for (int32_t k = 0; k < n; ++k) maxpx = std::max<int64_t>(maxpx, imgs[k].H * imgs[k].W);
-  const Resolved rp = resolve_params(params, dtype, conn, 1, maxpx);
+  Resolved rp = resolve_params(params, dtype, conn, 1, maxpx);
+  rp.flip = flip_of(flags);
   const Variant v{dtype, conn, rp.tile_h};
   if (!variant_supported(v)) return IWPP_E_UNSUPPORTED;
   std::vector<DevImage> h(n);
@@ -660,6 +682,7 @@ int iwpp_batch_create(const iwpp_image* imgs, int32_t n, int dtype, int conn, ui
   b->conn = conn;
   b->flags = flags;
   b->rp = resolve_params(params, dtype, conn, 1, maxpx);
+  b->rp.flip = flip_of(flags);
   if (b->rp.mode != 0) b->rp.mode = 0;  // plans always use the persistent kernel
   b->v = Variant{dtype, conn, b->rp.tile_h};
   if (!variant_supported(b->v)) {

@@ -70,6 +70,7 @@ struct KParams {
   int32_t first_round;  // host-driven rounds: this is the first round
   int32_t seed_queue_max;  // re-visits with at most this many halo receivers skip the scans
   uint32_t queue_waves;    // queue waves before a tile falls back to sweep rounds
+  uint32_t flip;           // 0: dilation; ~0u: erosion (values complemented in the tile)
   int32_t nq;           // tile queues in use (1..kMaxQueues)
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
@@ -91,6 +92,9 @@ hipError_t launch_round(const Variant& v, const DevImage& one, const DevImage* i
                         uint8_t* visited, hipStream_t st);
 hipError_t launch_clear_round(DevCtl* ctl, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// out <- image on the 1-pixel frame, the highest value inside (fill-holes marker).
+hipError_t launch_frame_marker(int dtype, void* out, const void* img, int64_t H, int64_t W,
+                               int64_t ld, hipStream_t st);
 int persistent_blocks_per_cu(const Variant& v);
 
 constexpr int kTileW = 64;    // one lane per tile column

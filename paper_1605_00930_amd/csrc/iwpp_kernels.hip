@@ -115,6 +115,16 @@ template <>
 struct Lowest<int32_t> {
   static constexpr int v = INT_MIN;
 };
+template <typename T>
+struct Highest;
+template <>
+struct Highest<uint8_t> {
+  static constexpr uint8_t v = 255;
+};
+template <>
+struct Highest<int32_t> {
+  static constexpr int32_t v = INT_MAX;
+};
 
 // LDS image of one tile plus a 1-pixel halo.  Interior pixel (y, x),
 // 0 <= y < TH, 0 <= x < TW, lives at (y + 1) * P + (x + 1).  The pitch is
@@ -161,6 +171,12 @@ struct Tile {
   static_assert(TH % 32 == 0 && G::NPIX <= 32768, "queue entries are 15-bit");
 
   __device__ static int lane() { return threadIdx.x; }
+  // Memory <-> tile value.  `flip` is 0 for reconstruction by dilation and
+  // all ones for reconstruction by erosion: bitwise NOT reverses the order of
+  // both pixel types, so the tile holds the complemented images and the
+  // dilation machinery computes the erosion (duality).
+  __device__ static int in(T raw, uint32_t flip) { return (int)(T)(raw ^ (T)flip); }
+  __device__ static T out(T v, uint32_t flip) { return (T)(v ^ (T)flip); }
   __device__ static int jv(const L& s, int y, int x) { return (int)s.J[G::at(y, x)]; }
   __device__ static int iv(const L& s, int y, int x) { return (int)s.I[G::at(y, x)]; }
 
@@ -181,7 +197,8 @@ struct Tile {
   // a value.  J is clamped to I on load (a clamped pixel's row is marked
   // dirty so that the clamp reaches memory); returns true if a first visit
   // saw J > I inside the tile.
-  __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first) {
+  __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
+                              uint32_t flip) {
     const T* __restrict__ gJ = (const T*)im.J;
     const T* __restrict__ gI = (const T*)im.I;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
@@ -208,8 +225,8 @@ struct Tile {
         const int64_t gy = gy0 + k;
         j[k] = i[k] = LO;
         if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
-          j[k] = (int)ld_coherent(&pj[k * im.ld]);
-          i[k] = (int)pi[k * im.ld];
+          j[k] = in(ld_coherent(&pj[k * im.ld]), flip);
+          i[k] = in(pi[k * im.ld], flip);
         }
       }
       if (yb == 0) {
@@ -220,8 +237,8 @@ struct Tile {
           const int64_t ey = y0 + yy - 1, ex = x0 + c - 1;
           ej[k] = ei[k] = LO;
           if (e < NE && ey >= 0 && ey < im.H && ex < im.W) {
-            ej[k] = (int)ld_coherent(&gJ[ey * im.ld + ex]);
-            ei[k] = (int)gI[ey * im.ld + ex];
+            ej[k] = in(ld_coherent(&gJ[ey * im.ld + ex]), flip);
+            ei[k] = in(gI[ey * im.ld + ex], flip);
           }
         }
       }
@@ -276,7 +293,8 @@ struct Tile {
 
   // Re-read the halo of J; the tile's own pixels in LDS are current because
   // this wavefront is their only writer.
-  __device__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0) {
+  __device__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
+                                     uint32_t flip) {
     const T* __restrict__ gJ = (const T*)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     for (int e = lane(); e < G::HALO; e += 64) {
@@ -297,7 +315,7 @@ struct Tile {
       const int64_t gy = y0 + y, gx = x0 + x;
       if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
         const int i = iv(s, y, x);
-        const int j = (int)ld_coherent(&gJ[gy * im.ld + gx]);
+        const int j = in(ld_coherent(&gJ[gy * im.ld + gx]), flip);
         s.J[G::at(y, x)] = (T)imin(j, i);
       }
     }
@@ -306,7 +324,8 @@ struct Tile {
     wsync();
   }
 
-  __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0) {
+  __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
+                               uint32_t flip) {
     T* __restrict__ gJ = (T*)im.J;
     const int64_t gx = x0 + lane();
     const bool col_in = gx < im.W;
@@ -317,7 +336,7 @@ struct Tile {
         const int y = g + __builtin_ctzll(rows);
         rows &= rows - 1;
         const int64_t gy = y0 + y;
-        if (gy < im.H && col_in) st_coherent(&gJ[gy * im.ld + gx], s.J[G::at(y, lane())]);
+        if (gy < im.H && col_in) st_coherent(&gJ[gy * im.ld + gx], out(s.J[G::at(y, lane())], flip));
       }
     }
   }
@@ -971,7 +990,7 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
     const bool first = ld_coherent(&visited[t]) == 0;
     VisitStats vs;
     bool hit = false;
-    const bool viol = TP::load(s, im, y0, x0, first);
+    const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
     if (lead) pre = prefetch_ticket(ctl, kp, q);
@@ -980,7 +999,7 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
     uint32_t c3 = (uint32_t)now();
     ws.t_solve += c3 - c2;
     for (;;) {
-      TP::store(s, im, y0, x0);
+      TP::store(s, im, y0, x0, kp.flip);
       const uint32_t act = TP::activation_mask(s);
       uint32_t c3b = (uint32_t)now();
       ws.t_store += c3b - c3;
@@ -1000,7 +1019,7 @@ __global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage*
       // a neighbour changed while this tile ran: reload the halo, continue
       vs = VisitStats();
       hit = false;
-      TP::reload_halo(s, im, y0, x0);
+      TP::reload_halo(s, im, y0, x0, kp.flip);
       uint32_t c5 = (uint32_t)now();
       ws.t_load += c5 - c4;
       TP::solve(s, kp.sweeps, true, kp.seed_queue_max, kp.queue_waves, kp.spin_limit, vs,
@@ -1035,10 +1054,10 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   const bool first = visited[t] == 0;
   VisitStats vs;
   bool hit = false;
-  const bool viol = TP::load(s, im, y0, x0, first);
+  const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
   TP::solve(s, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit, vs,
                 hit);
-  TP::store(s, im, y0, x0);
+  TP::store(s, im, y0, x0, kp.flip);
   const uint32_t act = TP::activation_mask(s);
   if (threadIdx.x == 0) {
     WorkerStats ws;
@@ -1180,6 +1199,40 @@ hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* sta
 
 hipError_t launch_clear_round(DevCtl* ctl, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_round, dim3(1), dim3(1), 0, st, ctl);
+  return hipGetLastError();
+}
+
+// Fill-holes marker (the "Fill Holes" subsection of the IWPP chapter): the
+// image itself on its 1-pixel frame and the highest value everywhere else;
+// reconstruction by erosion of the image from it lowers every region that
+// the frame reaches to what the frame lets through and leaves the holes (the
+// regions it cannot reach) filled to the level of their surroundings.
+template <typename T>
+__global__ __launch_bounds__(256) void k_frame_marker(T* __restrict__ out,
+                                                      const T* __restrict__ img, int64_t H,
+                                                      int64_t W, int64_t ld) {
+  for (int64_t y = blockIdx.y; y < H; y += gridDim.y) {
+    const bool edge_row = y == 0 || y == H - 1;
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < W;
+         x += (int64_t)gridDim.x * 256) {
+      const bool frame = edge_row || x == 0 || x == W - 1;
+      out[y * ld + x] = frame ? img[y * ld + x] : Highest<T>::v;
+    }
+  }
+}
+
+hipError_t launch_frame_marker(int dtype, void* out, const void* img, int64_t H, int64_t W,
+                               int64_t ld, hipStream_t st) {
+  int64_t gx = (W + 255) / 256, gy = H;
+  if (gx > 64) gx = 64;
+  if (gy > 65535) gy = 65535;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_frame_marker<uint8_t>, grid, dim3(256), 0, st, (uint8_t*)out,
+                       (const uint8_t*)img, H, W, ld);
+  else
+    hipLaunchKernelGGL(k_frame_marker<int32_t>, grid, dim3(256), 0, st, (int32_t*)out,
+                       (const int32_t*)img, H, W, ld);
   return hipGetLastError();
 }
 

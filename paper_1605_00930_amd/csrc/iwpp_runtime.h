@@ -22,6 +22,7 @@ struct Resolved {
   int timing;
   int seed_queue_max;
   uint32_t queue_waves;
+  uint32_t flip;  // 0 dilation, ~0u erosion (from IWPP_FLAG_EROSION)
 };
 
 // Device buffers of one launch context (a stream workspace, a batch plan or a

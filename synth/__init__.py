@@ -266,6 +266,43 @@ def random_pair(rng: np.random.Generator, H: int, W: int, dtype, kind: str = "un
     return I.astype(dtype), J.astype(dtype)
 
 
+def random_pair_above(rng: np.random.Generator, H: int, W: int, dtype,
+                      kind: str = "uniform", levels: int | None = None):
+    """A random (I, J) with J >= I, for reconstruction by erosion.
+
+    kind: "uniform"  I uniform over the dtype (or ``levels`` values), J
+                     between I and the top of the range, scaled by U[0,1);
+          "sparse"   J at the top of the range except a few pixels equal to I;
+          "plateau"  few levels, large flat zones (many ties);
+          "extreme"  values at the ends of the dtype range.
+    """
+    dtype = np.dtype(dtype)
+    if dtype == np.uint8:
+        lo, hi = 0, 255
+    else:
+        lo, hi = -(2 ** 31), 2 ** 31 - 1
+    top = hi if levels is None else lo + levels - 1
+    if kind == "uniform":
+        I = rng.integers(lo, top, size=(H, W), endpoint=True, dtype=np.int64)
+        J = I + np.floor((top - I) * rng.random((H, W))).astype(np.int64)
+    elif kind == "sparse":
+        I = rng.integers(lo, top, size=(H, W), endpoint=True, dtype=np.int64)
+        J = np.full((H, W), top, dtype=np.int64)
+        m = rng.random((H, W)) < 0.02
+        J[m] = I[m]
+    elif kind == "plateau":
+        L = rng.integers(2, 5)
+        vals = np.sort(rng.integers(lo, top, size=L, endpoint=True, dtype=np.int64))
+        I = vals[rng.integers(0, L, size=(H, W))]
+        J = np.where(rng.random((H, W)) < 0.05, I, vals[-1])
+    elif kind == "extreme":
+        I = np.where(rng.random((H, W)) < 0.5, lo, lo + 1).astype(np.int64)
+        J = np.where(rng.random((H, W)) < 0.1, I, hi).astype(np.int64)
+    else:
+        raise ValueError(kind)
+    return I.astype(dtype), J.astype(dtype)
+
+
 def sha256(*arrays: np.ndarray) -> str:
     h = hashlib.sha256()
     for a in arrays:

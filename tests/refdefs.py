@@ -82,3 +82,38 @@ def line_closed_form(J: np.ndarray, I: np.ndarray) -> np.ndarray:
     for x in range(n - 1, -1, -1):
         B[x] = min(i[x], max(j[x], B[x + 1])) if x < n - 1 else j[x]
     return np.maximum(L, B).astype(I.dtype).reshape(J.shape)
+
+
+# ------------------------------------------------------------ by erosion
+
+
+def _footprint(conn: int) -> np.ndarray:
+    return np.ones((3, 3), bool) if conn == 8 else ndimage.generate_binary_structure(2, 1)
+
+
+def brute_erode_scipy(J: np.ndarray, I: np.ndarray, conn: int) -> np.ndarray:
+    """Reconstruction by erosion by its definition: J <- max(erode(J), I)
+    until stable, with ``scipy.ndimage.grey_erosion`` as the elementary
+    erosion (pixels outside the image are the type's highest value, so they
+    never win a minimum)."""
+    hi = int(np.iinfo(J.dtype).max)
+    fp = _footprint(conn)
+    R = J.copy()
+    while True:
+        nxt = np.maximum(ndimage.grey_erosion(R, footprint=fp, mode="constant", cval=hi), I)
+        if np.array_equal(nxt, R):
+            return R
+        R = nxt
+
+
+def fill_holes_by_levels(image: np.ndarray, conn: int) -> np.ndarray:
+    """Grayscale fill-holes by threshold decomposition: for every level t,
+    {fill(I) >= t} is ``scipy.ndimage.binary_fill_holes({I >= t})`` with the
+    background connectivity `conn` (a flat increasing operator commutes with
+    thresholding); the grayscale result is the largest such t."""
+    st = _footprint(conn)
+    out = np.full(image.shape, np.iinfo(image.dtype).min, dtype=np.int64)
+    for t in np.unique(image):
+        filled = ndimage.binary_fill_holes(image >= t, structure=st)
+        out[filled] = np.maximum(out[filled], int(t))
+    return out.astype(image.dtype)

@@ -68,6 +68,7 @@ def test_argument_errors_before_gpu_work(lib):
     assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 0, None, None) == E
     im = iwpp.Image(a, b, 4, 4, 0)
     assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 4, None, None) == E  # flags
+    assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 8, None, None) == E
     p = iwpp.Params()
     p.tile_h = 48
     assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 0, ctypes.byref(p), None) == E
@@ -82,6 +83,13 @@ def test_argument_errors_before_gpu_work(lib):
     h = ctypes.c_void_p()
     assert lib.iwpp_batch_create(arr, 1, 0, 8, 0, None, ctypes.byref(h)) == E
     assert lib.iwpp_device_copy(a, b, 15, None) == E
+    # fill holes: overlap, sizes, pitch, dtype, connectivity
+    assert lib.iwpp_fill_holes_async(a, a, 4, 4, 0, 0, 8, None, None) == E
+    assert lib.iwpp_fill_holes_async(a, b, 0, 4, 0, 0, 8, None, None) == E
+    assert lib.iwpp_fill_holes_async(a, b, 4, 4, 3, 0, 8, None, None) == E
+    assert lib.iwpp_fill_holes_async(a, b, 4, 4, 0, 7, 8, None, None) == E
+    assert lib.iwpp_fill_holes_async(a, b, 4, 4, 0, 0, 5, None, None) == E
+    assert lib.iwpp_fill_holes_async(None, b, 4, 4, 0, 0, 8, None, None) == E
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

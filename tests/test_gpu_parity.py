@@ -228,6 +228,89 @@ def test_batch_plan_graph_replays(iwpp):
     plan.close()
 
 
+# ------------------------------------------------------------------ by erosion / fill holes
+
+
+def expect_erode(I, J, conn, clamp=False):
+    rc, R = oracle.reconstruct_erode(J, I, conn, clamp=clamp)
+    assert rc == oracle.OK
+    return R
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.int32])
+@pytest.mark.parametrize("conn", [8, 4])
+def test_erosion_fuzz_shapes(iwpp, dtype, conn):
+    rng = np.random.default_rng(300 + conn + (dtype == np.int32))
+    for (H, W) in SIZES + [(300, 257)]:
+        for kind in ("uniform", "sparse", "plateau", "extreme"):
+            I, J = synth.random_pair_above(rng, H, W, dtype, kind,
+                                           levels=8 if kind == "uniform" else None)
+            announce("erosion %dx%d %s %s conn %d" % (H, W, np.dtype(dtype).name, kind, conn))
+            got, _ = run(iwpp, I, J, conn, erosion=True)
+            same(got, expect_erode(I, J, conn), "erosion %dx%d %s" % (H, W, kind))
+
+
+def test_erosion_marker_below_mask(iwpp):
+    rng = np.random.default_rng(5)
+    I, J = synth.random_pair_above(rng, 150, 170, np.uint8, "uniform", levels=20)
+    J = J.copy()
+    J[40, 41] = 0
+    I[40, 41] = 9
+    announce("erosion marker<mask error path")
+    _, st = run(iwpp, I, J, 8, check=False, erosion=True)
+    assert st["rc"] == iwpp.E_MARKER_GT_MASK
+    got, st = run(iwpp, I, J, 8, clamp=True, erosion=True)
+    assert st["rc"] == iwpp.OK
+    same(got, expect_erode(I, J, 8, clamp=True), "erosion clamped")
+
+
+def test_erosion_batched(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(8)
+    batch = [synth.random_pair_above(rng, h, w, np.int32, "uniform", levels=30)
+             for h, w in [(70, 300), (257, 64), (5, 5), (190, 211)]]
+    pairs = [(torch.from_numpy(J).to(dev), torch.from_numpy(I).to(dev)) for I, J in batch]
+    announce("erosion batched 4 images")
+    iwpp.reconstruct_batched(pairs, 8, erosion=True)
+    for k, (I, J) in enumerate(batch):
+        same(pairs[k][0].cpu().numpy(), expect_erode(I, J, 8), "erosion batched %d" % k)
+
+
+def fill(iwpp, img, conn, **kw):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(img)).to(torch.device("cuda:0"))
+    out, st = iwpp.fill_holes(t, None, conn, **kw)
+    return out.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fill_holes_ellipses(iwpp, conn):
+    I, _ = synth.c2(H=777, W=1000)
+    announce("fill holes 777x1000 u8 conn %d" % conn)
+    got, _ = fill(iwpp, I, conn)
+    rc, want = oracle.fill_holes(I, conn)
+    assert rc == oracle.OK
+    same(got, want, "fill holes")
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_fill_holes_i32_and_small(iwpp, conn):
+    rng = np.random.default_rng(21 + conn)
+    cases = [synth.smooth_field_i32(3, 200, 333) - (1 << 19)]
+    for (H, W) in [(1, 1), (1, 50), (50, 1), (2, 2), (3, 3), (65, 63), (130, 70)]:
+        cases.append(rng.integers(-5, 5, size=(H, W)).astype(np.int32) * 1000)
+        cases.append(rng.integers(0, 4, size=(H, W)).astype(np.uint8) * 60)
+    for img in cases:
+        announce("fill holes %dx%d %s conn %d" % (img.shape[0], img.shape[1], img.dtype, conn))
+        got, _ = fill(iwpp, img, conn)
+        rc, want = oracle.fill_holes(img, conn)
+        assert rc == oracle.OK
+        same(got, want, "fill holes %s" % (img.shape,))
+
+
 # ------------------------------------------------------------------ full sizes
 
 
