@@ -70,7 +70,17 @@ __device__ __forceinline__ T ld_coherent(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ T ld_coherent(gptr<const T> p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
 __device__ __forceinline__ void st_coherent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coherent(__attribute__((address_space(1))) T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -83,15 +93,6 @@ __device__ __forceinline__ void drain_memory() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Lane i receives v from lane i-1; lane 0 receives `fill`.
-__device__ __forceinline__ int from_left(int v, int fill) {
-  return __builtin_amdgcn_update_dpp(fill, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
-}
-// Lane i receives v from lane i+1; lane 63 receives `fill`.
-__device__ __forceinline__ int from_right(int v, int fill) {
-  return __builtin_amdgcn_update_dpp(fill, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
 }
 
 // Orders this wavefront's LDS accesses before and after the call (a
@@ -199,11 +200,27 @@ struct Tile {
   // saw J > I inside the tile.
   __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
                               uint32_t flip) {
-    const T* __restrict__ gJ = (const T*)im.J;
-    const T* __restrict__ gI = (const T*)im.I;
+    // almost every tile lies inside the image with its halo: its loads need
+    // no bounds checks and its two row batches are unrolled
+    const bool inner = y0 >= 1 && y0 + TH < im.H && x0 >= 1 && x0 + TW < im.W;
+    return inner ? load_t<true>(s, im, y0, x0, first, flip)
+                 : load_t<false>(s, im, y0, x0, first, flip);
+  }
+  template <bool INNER>
+  __device__ static bool load_t(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
+                                uint32_t flip) {
+    // image rows live in global memory: address-space-1 pointers give
+    // global_load instructions, which (unlike flat ones) leave the LDS
+    // counter alone
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    const gptr<const T> gI = (gptr<const T>)im.I;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     wsync();
     bool viol = false;
+    // raw values are loaded under the bounds checks and complemented after
+    // the batch, so no load waits for its own data; a pixel outside the image
+    // starts as the raw encoding of LO
+    const int lo_raw = in((T)LO, flip);
     // Lanes 0..63 cover padded columns 0..63 (the left halo column and tile
     // columns 0..62), B rows per batch; padded columns 64 and 65 (tile column
     // 63 and the right halo column) of all rows are spread over the lanes and
@@ -214,19 +231,18 @@ struct Tile {
     const int64_t gx = x0 + lane() - 1;
     const bool c_in = gx >= 0 && gx < im.W;
     int ej[K], ei[K];
-#pragma unroll 1
-    for (int yb = 0; yb < G::ROWS; yb += B) {
+    auto batch = [&](const int yb) {
       int j[B], i[B];
       const int64_t gy0 = y0 + yb - 1;
-      const T* pj = gJ + gy0 * im.ld + gx;
-      const T* pi = gI + gy0 * im.ld + gx;
+      const gptr<const T> pj = gJ + gy0 * im.ld + gx;
+      const gptr<const T> pi = gI + gy0 * im.ld + gx;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int64_t gy = gy0 + k;
-        j[k] = i[k] = LO;
-        if (yb + k < G::ROWS && gy >= 0 && gy < im.H && c_in) {
-          j[k] = in(ld_coherent(&pj[k * im.ld]), flip);
-          i[k] = in(pi[k * im.ld], flip);
+        j[k] = i[k] = lo_raw;
+        if (yb + k < G::ROWS && (INNER || (gy >= 0 && gy < im.H && c_in))) {
+          j[k] = (int)ld_coherent(&pj[k * im.ld]);
+          i[k] = (int)pi[k * im.ld];
         }
       }
       if (yb == 0) {
@@ -235,10 +251,10 @@ struct Tile {
           const int e = lane() + 64 * k;
           const int yy = e >> 1, c = 64 + (e & 1);
           const int64_t ey = y0 + yy - 1, ex = x0 + c - 1;
-          ej[k] = ei[k] = LO;
-          if (e < NE && ey >= 0 && ey < im.H && ex < im.W) {
-            ej[k] = in(ld_coherent(&gJ[ey * im.ld + ex]), flip);
-            ei[k] = in(gI[ey * im.ld + ex], flip);
+          ej[k] = ei[k] = lo_raw;
+          if (e < NE && (INNER || (ey >= 0 && ey < im.H && ex < im.W))) {
+            ej[k] = (int)ld_coherent(&gJ[ey * im.ld + ex]);
+            ei[k] = (int)gI[ey * im.ld + ex];
           }
         }
       }
@@ -246,8 +262,8 @@ struct Tile {
       for (int k = 0; k < B; ++k) {
         const int yy = yb + k;
         if (yy >= G::ROWS) continue;
-        int a = j[k];
-        const int b = i[k];
+        int a = in((T)j[k], flip);
+        const int b = in((T)i[k], flip);
         if (a > b) {
           if (yy >= 1 && yy <= TH && lane() >= 1) {
             viol = viol || first;
@@ -258,14 +274,21 @@ struct Tile {
         s.J[yy * G::P + lane()] = (T)a;
         s.I[yy * G::P + lane()] = (T)b;
       }
+    };
+    if (INNER) {
+#pragma unroll
+      for (int yb = 0; yb < G::ROWS; yb += B) batch(yb);
+    } else {
+#pragma unroll 1
+      for (int yb = 0; yb < G::ROWS; yb += B) batch(yb);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int e = lane() + 64 * k;
       if (e >= NE) continue;
       const int yy = e >> 1, c = 64 + (e & 1);
-      int a = ej[k];
-      const int b = ei[k];
+      int a = in((T)ej[k], flip);
+      const int b = in((T)ei[k], flip);
       if (a > b) {
         if (yy >= 1 && yy <= TH && c == 64) {
           viol = viol || first;
@@ -326,7 +349,7 @@ struct Tile {
 
   __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
                                uint32_t flip) {
-    T* __restrict__ gJ = (T*)im.J;
+    const gptr<T> gJ = (gptr<T>)im.J;
     const int64_t gx = x0 + lane();
     const bool col_in = gx < im.W;
     for (int g = 0; g < TH; g += 64) {
@@ -347,29 +370,35 @@ struct Tile {
   // paid once per batch instead of once per step; every pixel of a pass has a
   // single writer, so loading ahead is safe.  Changed rows are collected as
   // ballot bits in `d` (wave-uniform) and written to rowdirty by the caller.
-  static constexpr int B = 16;
-
-  __device__ static void mark_rows(uint64_t& d0, uint64_t& d1, int y) {
-    if (y < 64)
-      d0 |= 1ull << y;
-    else
-      d1 |= 1ull << (y - 64);
+  // t <- max(t, prev of the lane on the left, prev of the lane on the right).
+  // A DPP lane whose source lane is outside the wavefront is not written, so
+  // lane 0 (no left lane) and lane 63 (no right lane) keep their t for that
+  // side.  The s_nop gives the two wait states a DPP read of a VGPR needs
+  // after a VALU write of it, whatever the compiler scheduled before.
+  __device__ static int max_sides(int t, int prev) {
+    asm("s_nop 1\n\t"
+        "v_max_i32_dpp %0, %1, %0 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_max_i32_dpp %0, %1, %0 wave_shl:1 row_mask:0xf bank_mask:0xf"
+        : "+v"(t)
+        : "v"(prev));
+    return t;
   }
 
-  // Downward (D = +1) or upward (D = -1) pass; lane = column.
+  // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
+  // min(I, max(J, the three pixels of the previous row around it)).  The
+  // previous row stays in `prev`; its diagonal neighbours come from the lanes
+  // beside.  Lanes 0 and 63 also take the halo column beside them (`fprev`,
+  // the previous row's halo pixel); the other lanes read their own column
+  // there, an old value that never exceeds `prev`, so every lane runs the
+  // same instructions.  Changed rows are recorded per batch of B rows.
+  static constexpr int B = 16;
   template <int D>
   __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
     const int ys = D > 0 ? 0 : TH - 1;
-    int pc = jv(s, ys - D, x);
-    int pl = LO, pr = LO;
-    if (CONN == 8) {
-      pl = jv(s, ys - D, x - 1);
-      pr = jv(s, ys - D, x + 1);
-    }
-    // the halo column a DPP shift brings into this lane: lane 0 reads the
-    // left halo, lane 63 the right halo (other lanes' values are unused)
-    const int fx = x == 0 ? -1 : TW;
+    const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
+    int prev = jv(s, ys - D, x);
+    int fprev = CONN == 8 ? jv(s, ys - D, fx) : LO;
 #pragma unroll 1
     for (int kb = 0; kb < TH; kb += B) {
       int jj[B], ii[B], ff[B];
@@ -380,42 +409,51 @@ struct Tile {
         ii[k] = iv(s, y, x);
         if (CONN == 8) ff[k] = jv(s, y, fx);
       }
+      bool changed = false;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        int m = imax(jj[k], pc);
-        if (CONN == 8) m = imax(m, imax(pl, pr));
-        const int v = imin(m, ii[k]);
-        if (__ballot(v != jj[k])) mark_rows(d0, d1, ys + D * (kb + k));
-        jj[k] = v;
-        pc = v;
+        int t = imax(jj[k], prev);
         if (CONN == 8) {
-          pl = from_left(v, ff[k]);
-          pr = from_right(v, ff[k]);
+          t = max_sides(imax(t, fprev), prev);
+          fprev = ff[k];
         }
+        const int v = imin(t, ii[k]);
+        changed = changed || v != jj[k];
+        jj[k] = v;
+        prev = v;
       }
 #pragma unroll
       for (int k = 0; k < B; ++k) s.J[G::at(ys + D * (kb + k), x)] = (T)jj[k];
+      if (__ballot(changed)) {
+        // rows kb .. kb + B - 1 of the pass, i.e. this block of tile rows
+        const int y0 = D > 0 ? kb : TH - kb - B;
+        const uint64_t blk = ((1ull << B) - 1) << (y0 & 63);
+        if (y0 < 64)
+          d0 |= blk;
+        else
+          d1 |= blk;
+      }
     }
   }
 
-  // Rightward (D = +1) or leftward (D = -1) pass; lane = row of a 64-row
-  // group, groups taken top to bottom.
+  // Right (D = +1) or left (D = -1) pass, one lane per row, in groups of 64
+  // rows.  Lane 0 also takes the row above the group and lane 63 the row
+  // below it; other lanes read their own row there (harmless, as above).  In
+  // 32-row tiles lanes 32..63 follow the halo row below the tile: what they
+  // compute is min(I, max of valid lower bounds of R), itself a valid lower
+  // bound of R, which is all lane 31 needs from its lower neighbour; they
+  // write nothing.
   template <int D>
   __device__ static void pass_horz(L& s, uint64_t& d0, uint64_t& d1) {
 #pragma unroll 1
     for (int g = 0; g < TH; g += 64) {
-      const int nrows = TH - g < 64 ? TH - g : 64;  // 32-row tiles use half the lanes
+      const int nrows = TH - g < 64 ? TH - g : 64;
       const bool live = lane() < nrows;
-      const int yc = live ? g + lane() : g;  // dead lanes shadow row g
+      const int yc = live ? g + lane() : TH;
       const int xs = D > 0 ? 0 : TW - 1;
-      int pc = jv(s, yc, xs - D);
-      int pu = LO, pd = LO;
-      if (CONN == 8) {
-        pu = jv(s, yc - 1, xs - D);
-        pd = jv(s, yc + 1, xs - D);
-      }
-      // lane 0 gets the row above the group, the last live lane the row below
-      const int fy = lane() == 0 ? g - 1 : g + nrows;
+      const int fy = lane() == 0 ? g - 1 : (lane() == 63 && live ? g + 64 : yc);
+      int prev = jv(s, yc, xs - D);
+      int fprev = CONN == 8 ? jv(s, fy, xs - D) : LO;
       bool dirty = false;
 #pragma unroll 1
       for (int kb = 0; kb < TW; kb += B) {
@@ -429,17 +467,15 @@ struct Tile {
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-          int m = imax(jj[k], pc);
-          if (CONN == 8) m = imax(m, imax(pu, pd));
-          const int v = imin(m, ii[k]);
+          int t = imax(jj[k], prev);
+          if (CONN == 8) {
+            t = max_sides(imax(t, fprev), prev);
+            fprev = ff[k];
+          }
+          const int v = imin(t, ii[k]);
           dirty = dirty || v != jj[k];
           jj[k] = v;
-          pc = v;
-          if (CONN == 8) {
-            pu = from_left(v, ff[k]);
-            pd = from_right(v, ff[k]);
-            if (nrows < 64 && lane() == nrows - 1) pd = ff[k];
-          }
+          prev = v;
         }
         if (live) {
 #pragma unroll
@@ -454,8 +490,6 @@ struct Tile {
       wsync();
     }
   }
-
-  // One round of the four passes; true if any pixel of the tile rose.
   __device__ static bool sweep_round(L& s, VisitStats& vs) {
     uint64_t d0 = 0, d1 = 0;
     pass_vert<+1>(s, d0, d1);
