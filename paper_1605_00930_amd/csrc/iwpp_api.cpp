@@ -107,7 +107,7 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   Resolved r{};
   iwpp_params base{};
   base.tile_h = default_tile_h(dtype);
-  base.sweeps = dtype == IWPP_U8 ? 2 : 1;
+  base.sweeps = dtype == IWPP_U8 ? 4 : 1;
   base.mode = 0;
   base.seed_queue = 32;
   base.queue_waves = 4;
