@@ -263,6 +263,30 @@ int iwpp_fill_holes_async(const void *image, void *out, int64_t H, int64_t W, in
                           iwpp_stream_t stream);
 
 /*
+ * Euclidean distance transform as an irregular wavefront propagation ("Transformada de
+ * Distancia Euclidiana" subsection of the IWPP chapter and its distance-transform
+ * algorithm).  `image` is a uint8 device array (row pitch `ld_image`, 0 = W) whose 0
+ * pixels are background and others object.  Every background pixel is its own site;
+ * a pixel takes a neighbour's site (4- or 8-connected) whenever that site is strictly
+ * closer in Euclidean distance, until nothing changes.  Outputs (int32 device arrays,
+ * row pitch `ld_out`, 0 = W):
+ *   sites  the site each pixel ended with, packed (y << 16) | x, or -1 if the image
+ *          has no background pixel;
+ *   dist2  (may be NULL) the squared Euclidean distance to that site, or -1.
+ * Like the paper's algorithm this is the vector-propagation approximation of the exact
+ * transform: each site is a background pixel and dist2 is exact for it, but a few pixels
+ * may hold a site slightly farther than the nearest background pixel, and ties between
+ * equally close sites may resolve differently from run to run.  H and W are at most
+ * 32768.  Arrays must not overlap; the int32 arrays must be 4-byte aligned.  Only the
+ * tile height 32 and the persistent mode exist (other values of tile_h or mode return
+ * IWPP_E_UNSUPPORTED); `max_tile_visits`, `grid`, `order_seed`, `spin_limit` and
+ * `timing` apply.  Asynchronous on `stream`; iwpp_stream_status() reports the result.
+ */
+int iwpp_edt_async(const void *image, int64_t ld_image, void *sites, void *dist2,
+                   int64_t ld_out, int64_t H, int64_t W, int conn, const iwpp_params *params,
+                   iwpp_stream_t stream);
+
+/*
  * Plain device-to-device streaming copy of `bytes` (a multiple of 16) with
  * the library's own kernel: the reference for bandwidth and for scaling
  * hardware byte counters.

@@ -173,3 +173,85 @@ static heap_ent heap_pop(heap_t *h) {
 #include "oracle_body.inc"
 #undef OT
 #undef OSUF
+
+/* ------------------------------------------------------------------ EDT */
+
+/* squared distance from pixel index p to site index v (W columns) */
+static int64_t sq_dist(int64_t p, int64_t v, int64_t W) {
+  const int64_t dy = p / W - v / W, dx = p % W - v % W;
+  return dy * dy + dx * dx;
+}
+
+int oracle_edt(const uint8_t *img, int64_t H, int64_t W, int conn, int32_t *sites,
+               int64_t *dist2, oracle_stats *st) {
+  if (!img || !sites || H < 1 || W < 1 || H > 32768 || W > 32768) return ORACLE_E_ARG;
+  if (conn != 4 && conn != 8) return ORACLE_E_ARG;
+  const nbr_t *nb = conn == 8 ? NALL8 : NALL4;
+  const int nn = conn;
+  const int64_t N = H * W;
+  /* VR as a pixel index, -1 for "no site" (infinitely far) */
+  int64_t *vr = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+  if (!vr) return ORACLE_E_NOMEM;
+  queue_t q;
+  if (queue_init(&q)) {
+    free(vr);
+    return ORACLE_E_NOMEM;
+  }
+  int64_t seeds = 0, pushes = 0, pops = 0;
+  /* initialisation phase */
+  for (int64_t p = 0; p < N; ++p) vr[p] = img[p] == 0 ? p : -1;
+  for (int64_t p = 0; p < N; ++p) {
+    if (img[p] != 0) continue;
+    const int64_t y = p / W, x = p % W;
+    int has_object = 0;
+    for (int k = 0; k < nn; ++k) {
+      const int64_t yy = y + nb[k].dy, xx = x + nb[k].dx;
+      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+      if (img[yy * W + xx] != 0) has_object = 1;
+    }
+    if (has_object) {
+      if (queue_push(&q, p)) goto nomem;
+      seeds++;
+    }
+  }
+  /* irregular propagation phase */
+  while (q.n > 0) {
+    const int64_t p = queue_pop_front(&q);
+    pops++;
+    const int64_t y = p / W, x = p % W;
+    for (int k = 0; k < nn; ++k) {
+      const int64_t yy = y + nb[k].dy, xx = x + nb[k].dx;
+      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+      const int64_t qi = yy * W + xx;
+      /* DIST(q, VR(p)) < DIST(q, VR(q)); "no site" is infinitely far */
+      if (vr[qi] < 0 || sq_dist(qi, vr[p], W) < sq_dist(qi, vr[qi], W)) {
+        vr[qi] = vr[p];
+        if (queue_push(&q, qi)) goto nomem;
+        pushes++;
+      }
+    }
+  }
+  /* distance map from the Voronoi sites */
+  for (int64_t p = 0; p < N; ++p) {
+    if (vr[p] < 0) {
+      sites[p] = -1;
+      if (dist2) dist2[p] = -1;
+    } else {
+      sites[p] = (int32_t)(((vr[p] / W) << 16) | (vr[p] % W));
+      if (dist2) dist2[p] = sq_dist(p, vr[p], W);
+    }
+  }
+  if (st) {
+    st->seeds = seeds;
+    st->pushes = pushes;
+    st->pops = pops;
+    st->iters = 0;
+  }
+  queue_free(&q);
+  free(vr);
+  return ORACLE_OK;
+nomem:
+  queue_free(&q);
+  free(vr);
+  return ORACLE_E_NOMEM;
+}

@@ -108,6 +108,22 @@ int oracle_pixels_i32(const int32_t *J, const int32_t *I, int64_t H,
                       const int64_t *cols, int64_t n, int64_t max_visit,
                       int32_t *out);
 
+/*
+ * Euclidean distance transform in IWPP form (the distance-transform
+ * algorithm of the IWPP chapter, "Transformada de Distancia Euclidiana"):
+ * pixels of `img` equal to 0 are background and are their own site VR;
+ * object pixels start with no site.  The initialisation queues every
+ * background pixel with an object neighbour; then a FIFO queue pops p and,
+ * for each neighbour q whose distance to VR(p) is strictly below its
+ * distance to VR(q), sets VR(q) = VR(p) and queues q.  Outputs:
+ *   sites[p]  VR(p) packed (y << 16) | x, or -1 for no site;
+ *   dist2[p]  squared Euclidean distance to VR(p), or -1 (may be NULL).
+ * H and W are at most 32768.  st (may be NULL) counts queued and popped
+ * pixels.
+ */
+int oracle_edt(const uint8_t *img, int64_t H, int64_t W, int conn, int32_t *sites,
+               int64_t *dist2, oracle_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,6 +108,7 @@ def _load():
         "iwpp_release_workspace": ([], i32),
         "iwpp_device_copy": ([vp, vp, ctypes.c_size_t, vp], i32),
         "iwpp_fill_holes_async": ([vp, vp, i64, i64, i64, i32, i32, P(Params), vp], i32),
+        "iwpp_edt_async": ([vp, i64, vp, vp, i64, i64, i64, i32, P(Params), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -234,6 +235,35 @@ def fill_holes(image, out=None, conn: int = 8, *, params=None, stream=None,
     if rc != OK:
         raise IwppError(rc, "iwpp_fill_holes_async")
     return out, stream_status(stream, check=check)
+
+
+def edt(image, conn: int = 8, *, sites=None, dist2=None, params=None, stream=None,
+        check: bool = True):
+    """Euclidean distance transform of a uint8 image (0 = background).
+    Returns (sites, dist2, counters): int32 tensors of nearest-site positions
+    packed (y << 16) | x and squared distances (-1 where there is no site)."""
+    import torch
+
+    if image.dim() != 2 or image.dtype != torch.uint8 or not image.is_cuda:
+        raise ValueError("edt takes a 2-D uint8 tensor on the GPU")
+    if image.stride(1) != 1:
+        raise ValueError("image rows must be contiguous")
+    H, W = image.shape
+    if sites is None:
+        sites = torch.empty((H, W), dtype=torch.int32, device=image.device)
+    if dist2 is None:
+        dist2 = torch.empty((H, W), dtype=torch.int32, device=image.device)
+    for t in (sites, dist2):
+        if t.shape != image.shape or t.dtype != torch.int32 or t.device != image.device:
+            raise ValueError("sites and dist2 must be int32 tensors shaped like the image")
+    if sites.stride() != dist2.stride() or sites.stride(1) != 1:
+        raise ValueError("sites and dist2 must share one contiguous row pitch")
+    rc = _load().iwpp_edt_async(image.data_ptr(), image.stride(0), sites.data_ptr(),
+                                dist2.data_ptr(), sites.stride(0), H, W, conn,
+                                _ptr(_params(params)), _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_edt_async")
+    return sites, dist2, stream_status(stream, check=check)
 
 
 def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, erosion: bool = False,

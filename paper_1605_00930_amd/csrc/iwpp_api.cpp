@@ -570,6 +570,58 @@ int iwpp_fill_holes_async(const void* image, void* out, int64_t H, int64_t W, in
   return iwpp_reconstruct_async(&im, dtype, conn, IWPP_FLAG_EROSION, params, stream);
 }
 
+int iwpp_edt_async(const void* image, int64_t ld_image, void* sites, void* dist2,
+                   int64_t ld_out, int64_t H, int64_t W, int conn, const iwpp_params* params,
+                   iwpp_stream_t stream) {
+  if (!image || !sites) return IWPP_E_ARG;
+  if (conn != 4 && conn != 8) return IWPP_E_ARG;
+  if (H < 1 || W < 1 || H > 32768 || W > 32768) return IWPP_E_ARG;
+  if ((ld_image != 0 && ld_image < W) || (ld_out != 0 && ld_out < W)) return IWPP_E_ARG;
+  const int64_t li = ld_image ? ld_image : W, lo = ld_out ? ld_out : W;
+  const uintptr_t a0 = (uintptr_t)image, s0 = (uintptr_t)sites, d0 = (uintptr_t)dist2;
+  if ((s0 | d0) & 3u) return IWPP_E_ARG;
+  const uintptr_t na = (uintptr_t)((H - 1) * li + W), ns = (uintptr_t)((H - 1) * lo + W) * 4;
+  auto overlap = [](uintptr_t p, uintptr_t np, uintptr_t q, uintptr_t nq) {
+    return p < q + nq && q < p + np;
+  };
+  if (overlap(a0, na, s0, ns)) return IWPP_E_ARG;
+  if (dist2 && (overlap(a0, na, d0, ns) || overlap(s0, ns, d0, ns))) return IWPP_E_ARG;
+  int rc = check_params(params);
+  if (rc) return rc;
+  Resolved rp = resolve_params(params, IWPP_I32, conn, H, W);
+  if ((params && params->tile_h && params->tile_h != 32) || (params && params->mode != 0))
+    return IWPP_E_UNSUPPORTED;
+  rp.tile_h = 32;
+  rp.mode = 0;
+  rp.flip = 0;
+  const Variant v{kDtypeEdt, conn, rp.tile_h};
+  if (!variant_supported(v)) return IWPP_E_UNSUPPORTED;
+  iwpp_image im{};
+  im.marker = sites;
+  im.mask = image;
+  im.H = H;
+  im.W = W;
+  im.ld = lo;
+  const DevImage one = make_dev_image(im, rp.tile_h, 0);
+  const int64_t ntiles = (int64_t)one.tiles_y * one.tiles_x;
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  rc = get_workspace(st, &w);
+  if (rc) return rc;
+  HIP_TRY(launch_edt_init(sites, lo, image, li, H, W, st));
+  w->buf.incomplete_rounds = false;
+  w->flags = 0;
+  w->nimg = 1;
+  w->ntiles = ntiles;
+  rc = enqueue(w->buf, v, rp, one, nullptr, 1, ntiles, st, &w->launches);
+  if (!rc && dist2) {
+    const hipError_t e = launch_edt_dist(dist2, sites, lo, H, W, st);
+    if (e != hipSuccess) rc = IWPP_E_HIP;
+  }
+  w->enqueue_rc = rc;
+  return rc;
+}
+
 int iwpp_stream_status(iwpp_stream_t stream, iwpp_stats* stats) {
   hipStream_t st = (hipStream_t)stream;
   Workspace* w = nullptr;

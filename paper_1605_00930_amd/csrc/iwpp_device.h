@@ -1,0 +1,406 @@
+// iwpp_device.h -- device-side pieces shared by the tile kernels: memory
+// primitives, per-visit and per-worker counters, the persistent tile queue
+// (tickets, ring slots, single-owner tile states, termination) and the
+// persistent worker loop, which is generic over the tile policy that loads,
+// solves and writes back one tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include "iwpp_internal.h"
+
+namespace iwpp {
+
+constexpr int TW = kTileW;  // 64: one lane per tile column
+static_assert(kThreads == 64, "one wavefront per tile");
+
+// ------------------------------------------------------------ primitives
+
+__device__ __forceinline__ uint32_t ld_rlx_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_rlx_i32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Marker pixels cross workgroups that may sit on different XCDs, each with
+// its own L2.  They are only ever read and written with agent-scope relaxed
+// atomic accesses: on gfx950 such a load is served coherently for the whole
+// device and such a store writes through, so no L2 write-back or invalidate
+// (what an agent-scope fence costs) is needed to hand a tile from one
+// workgroup to another.  Ordering comes from drain_memory() below.
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ T ld_coherent(gptr<const T> p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coherent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coherent(__attribute__((address_space(1))) T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every memory access this wavefront has issued is complete (an
+// agent-scope store is then visible to the whole device), and keep the
+// compiler from moving memory accesses across the wait.  Used after the
+// marker write-back, before the tile is published, and after a tile is
+// taken, before its marker is read.
+__device__ __forceinline__ void drain_memory() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Orders this wavefront's LDS accesses before and after the call (a
+// one-wavefront workgroup barrier; the compiler keeps its memory fences).
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint64_t now() { return wall_clock64(); }
+
+// Per-visit work counters, kept by the wavefront (uniform values).
+struct VisitStats {
+  uint32_t pushes = 0, rounds = 0, iters = 0, ovf = 0;
+};
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int find_image(const DevImage* imgs, int nimg, int64_t t) {
+  int lo = 0, hi = nimg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (imgs[mid].tile_base <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void add64(uint64_t* p, uint64_t v) {
+  if (v) atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+
+// Per-worker totals, flushed once when the worker exits.
+// 32-bit counts are enough for one worker within one launch (the wall clock
+// runs at 100 MHz, 43 s before a per-worker timer wraps).
+struct WorkerStats {
+  uint32_t pushes = 0, rounds = 0, iters = 0, ovf = 0, visits = 0, reproc = 0, requeued = 0;
+  uint32_t t_idle = 0, t_load = 0, t_solve = 0, t_store = 0, t_sync = 0;
+  __device__ void add(const VisitStats& v) {
+    pushes += v.pushes;
+    rounds += v.rounds;
+    iters += v.iters;
+    ovf += v.ovf;
+  }
+  __device__ void flush(DevCtl* ctl) const {
+    add64(&ctl->pushes, pushes);
+    add64(&ctl->sweeps, rounds);
+    add64(&ctl->qiters, iters);
+    add64(&ctl->overflows, ovf);
+    add64(&ctl->visits, visits);
+    add64(&ctl->reproc, reproc);
+    add64(&ctl->requeued, requeued);
+    add64(&ctl->t_idle, t_idle);
+    add64(&ctl->t_load, t_load);
+    add64(&ctl->t_solve, t_solve);
+    add64(&ctl->t_store, t_store);
+    add64(&ctl->t_sync, t_sync);
+  }
+};
+
+// ------------------------------------------------------------ persistent
+//
+// Tile queues.  Tile t belongs to queue (t / chunk) % nq; workgroup w
+// serves queue w % nq (workgroups are dealt to the 8 XCDs in turn, so a
+// queue's tiles are handled under one L2, and chunks of neighbouring tiles
+// are spread over all queues).  A pop is one atomicAdd on the queue head:
+// ticket h.  Tickets below the queue's first-pass length map directly to
+// the tiles of the initial pass (no ring traffic); later tickets wait on
+// their ring slot until a producer fills it.  The worker that brings the
+// pending count to zero marks the launch done and writes a stop value into
+// every slot a waiter may hold.
+
+constexpr int kSlotEmpty = -1;
+constexpr int kSlotStop = -3;
+
+__device__ __forceinline__ int queue_of(const KParams& kp, int64_t t) {
+  return (int)((t / kp.chunk) % kp.nq);
+}
+
+// Number of tiles of queue q's first pass: chunks q, q + nq, ...
+__device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
+  const int64_t nchunks = (kp.ntiles + kp.chunk - 1) / kp.chunk;
+  if (q >= nchunks) return 0;
+  const int64_t nc = (nchunks - 1 - q) / kp.nq + 1;
+  int64_t len = nc * kp.chunk;
+  if (q + (nc - 1) * kp.nq == nchunks - 1) len -= nchunks * kp.chunk - kp.ntiles;
+  return len;
+}
+
+__device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, int q, int64_t i) {
+  const int64_t c = (i / kp.chunk) * kp.nq + q;
+  const int64_t t = c * kp.chunk + i % kp.chunk;
+  if (kp.order_mul == 1 && kp.order_add == 0) return t;
+  return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);
+}
+
+__device__ __forceinline__ int* ring_slot(int* queue, const KParams& kp, int q, int64_t pos,
+                                          int64_t len) {
+  return &queue[(int64_t)q * kp.qcap + (pos - len) % (int64_t)kp.qcap];
+}
+
+// Enqueue tile n (the caller has just moved it from idle to pending).
+static __device__ void queue_push(DevCtl* ctl, int* queue, const KParams& kp, int n) {
+  const int q = queue_of(kp, n);
+  const uint32_t pos = atomicAdd(&ctl->tail[q].v, 1u);
+  __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// No more work: tell every waiter.  Executed by a whole wavefront.
+static __device__ void stop_all(DevCtl* ctl, int* queue, const KParams& kp, int grid) {
+  __hip_atomic_store(&ctl->done.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q = 0; q < kp.nq; ++q) {
+    const int64_t len = first_pass_len(kp, q);
+    const int64_t h = ld_rlx_u32(&ctl->head[q].v);
+    int64_t t = ld_rlx_u32(&ctl->tail[q].v);
+    if (t < len) t = len;
+    // waiters hold tickets in [tail, head); a worker that passed the `done`
+    // check but has not taken its ticket yet lands within `grid` more
+    const int64_t hi = (h > t ? h : t) + grid;
+    for (int64_t pos = t + threadIdx.x; pos < hi; pos += 64)
+      __hip_atomic_store(ring_slot(queue, kp, q, pos, len), kSlotStop, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, int grid, int bits) {
+  atomicOr((int*)&ctl->status.v, bits | ST_ABORT);
+  __hip_atomic_store(&ctl->done.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q = 0; q < kp.nq; ++q) {  // one lane: this path only ends a failed launch
+    const int64_t len = first_pass_len(kp, q);
+    const int64_t h = ld_rlx_u32(&ctl->head[q].v);
+    int64_t t = ld_rlx_u32(&ctl->tail[q].v);
+    if (t < len) t = len;
+    const int64_t hi = (h > t ? h : t) + grid;
+    for (int64_t pos = t; pos < hi; ++pos)
+      __hip_atomic_store(ring_slot(queue, kp, q, pos, len), kSlotStop, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Turn ticket h of queue q into a tile id, or -1 when the launch is over.
+// Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
+// the XCD, which a waiting worker must not do to the tiles others are
+// working on.
+static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
+                              int grid, uint32_t h) {
+  const int64_t len = first_pass_len(kp, q);
+  int v;
+  if ((int64_t)h < len) {
+    v = (int)first_pass_tile(kp, q, h);
+  } else {
+    int* slot = ring_slot(queue, kp, q, h, len);
+    uint32_t nap = 1;
+    for (uint32_t w = 0;; ++w) {
+      v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= 0) break;
+      if (v == kSlotStop) return -1;
+      if ((w & 63) == 63 && ld_rlx_u32(&ctl->done.v)) return -1;
+      if (w > kp.spin_limit) {
+        abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
+        return -1;
+      }
+      for (uint32_t k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(2);
+      if (nap < 16) nap <<= 1;
+    }
+    __hip_atomic_store(slot, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (kp.max_visits > 0) {
+    const uint32_t nv = atomicAdd(&ctl->visits_cap.v, 1u);
+    if ((int64_t)nv >= kp.max_visits) {
+      abort_launch(ctl, queue, kp, grid, ST_INCOMPLETE);
+      return -1;
+    }
+  }
+  // pending -> running.  A neighbour that asked for this visit finished its
+  // marker stores before its request reached the state word, so once the
+  // exchange is complete, the marker reads that follow see them.
+  __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  drain_memory();
+  return v;
+}
+
+constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
+
+// Take a tile id from queue q (using an already taken ticket if `pre` holds
+// one), or -1 when the launch is over.
+static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
+                         int grid, uint32_t pre) {
+  if (pre == kNoTicket) {
+    if (ld_rlx_u32(&ctl->done.v)) return -1;
+    pre = atomicAdd(&ctl->head[q].v, 1u);
+  }
+  return resolve_ticket(ctl, queue, kp, state, q, grid, pre);
+}
+
+// While queue q's first pass lasts, the next ticket is taken before the
+// current tile is solved, so its round trip overlaps useful work (a first-
+// pass ticket maps to a tile without waiting).
+static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q) {
+  if (ld_rlx_u32(&ctl->done.v)) return kNoTicket;
+  if ((int64_t)ld_rlx_u32(&ctl->head[q].v) >= first_pass_len(kp, q)) return kNoTicket;
+  return atomicAdd(&ctl->head[q].v, 1u);
+}
+
+// Publish the end of a visit of tile t (whole wavefront, once the tile's
+// marker write-back is complete).  Lanes 0..8
+// ask the neighbours in `act` for a visit while lane 9 tries to release t
+// (one round trip); then the pending count and the queue reservations of the
+// neighbours that were idle go out together (a second round trip), and only
+// after both have landed are the queue slots filled, so a queued tile is
+// always already counted.  Returns 1 if t must be run again (a neighbour
+// asked while it ran), 2 if this visit completed the launch, 0 otherwise.
+static __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
+                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act,
+                       WorkerStats& ws) {
+  const int d = threadIdx.x;
+  int n = -1;
+  if (d < 9 && ((act >> d) & 1u)) {
+    const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
+    if (ny >= 0 && ny < im.tiles_y && nx >= 0 && nx < im.tiles_x)
+      n = (int)(im.tile_base + ny * im.tiles_x + nx);
+  }
+  bool fresh = false;  // was idle: this wavefront enqueues it
+  bool released = false;
+  if (n >= 0)
+    fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  if (d == 9) {
+    uint32_t expect = TS_RUNNING;
+    released = __hip_atomic_compare_exchange_strong(
+        &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const int nfresh = __popcll(__ballot(fresh));
+  const bool rel = __ballot(released) != 0;
+  // count the new tiles and reserve their queue positions
+  const int delta = nfresh - (rel ? 1 : 0);
+  int last = 0;
+  if (d == 0 && delta != 0) {
+    const int old = atomicAdd((int*)&ctl->pending.v, delta);
+    last = old + delta == 0;
+  }
+  uint32_t pos = 0;
+  int q = 0;
+  if (fresh) {
+    q = queue_of(kp, n);
+    pos = atomicAdd(&ctl->tail[q].v, 1u);
+  }
+  int res = __builtin_amdgcn_readfirstlane(last) ? 2 : 0;
+  if (fresh)
+    __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  ws.requeued += nfresh;
+  if (!rel) {
+    // running | pending: take the request and run again (the failed release
+    // already saw the request, so the halo reads that follow see the
+    // neighbour's new border)
+    if (d == 0)
+      __hip_atomic_exchange(&state[t], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    drain_memory();
+    ws.reproc++;
+    ws.visits++;
+    res = 1;
+  }
+  return res;
+}
+
+// The body of a persistent tile worker, for any tile policy TP (the
+// reconstruction tile, the distance-transform tile): take tiles from the
+// queues, load, solve, write back, publish, until the launch ends.
+template <typename TP>
+__device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* __restrict__ imgs,
+                                                  KParams kp, DevCtl* ctl, int* queue,
+                                                  uint32_t* state, uint8_t* visited) {
+  constexpr int TH = TP::kTH;
+  __shared__ typename TP::L s;
+  const bool lead = threadIdx.x == 0;
+  const int q = blockIdx.x % kp.nq;
+  const int grid = gridDim.x;
+  WorkerStats ws;
+  uint32_t pre = kNoTicket;  // lane 0: a ticket taken ahead of time
+  for (;;) {
+    uint32_t c0 = (uint32_t)now();
+    int t = 0;
+    if (lead) {
+      t = queue_pop(ctl, queue, kp, state, q, grid, pre);
+      pre = kNoTicket;
+    }
+    t = __builtin_amdgcn_readfirstlane(t);
+    uint32_t c1 = (uint32_t)now();
+    ws.t_idle += c1 - c0;
+    if (t < 0) break;
+    ws.visits++;
+    const int k = imgs ? find_image(imgs, kp.nimg, t) : 0;
+    const DevImage im = imgs ? imgs[k] : one;
+    const int64_t tl = (int64_t)t - im.tile_base;
+    const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
+    const int64_t y0 = ty * TH, x0 = tx * TW;
+    const bool first = ld_coherent(&visited[t]) == 0;
+    VisitStats vs;
+    bool hit = false;
+    const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
+    uint32_t c2 = (uint32_t)now();
+    ws.t_load += c2 - c1;
+    if (lead) pre = prefetch_ticket(ctl, kp, q);
+    TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
+              vs, hit);
+    uint32_t c3 = (uint32_t)now();
+    ws.t_solve += c3 - c2;
+    for (;;) {
+      TP::store(s, im, y0, x0, kp.flip);
+      const uint32_t act = TP::activation_mask(s, y0, x0);
+      uint32_t c3b = (uint32_t)now();
+      ws.t_store += c3b - c3;
+      ws.add(vs);
+      if (lead) {
+        if (first) st_coherent(&visited[t], (uint8_t)1);
+        if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
+        if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
+      }
+      // the write-back is complete before anyone is told about it
+      drain_memory();
+      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
+      if (res == 2) stop_all(ctl, queue, kp, grid);
+      uint32_t c4 = (uint32_t)now();
+      ws.t_sync += c4 - c3b;
+      if (res != 1) break;
+      // a neighbour changed while this tile ran: reload the halo, continue
+      vs = VisitStats();
+      hit = false;
+      TP::reload_halo(s, im, y0, x0, kp.flip);
+      uint32_t c5 = (uint32_t)now();
+      ws.t_load += c5 - c4;
+      TP::solve(s, y0, x0, kp.sweeps, true, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
+                vs, hit);
+      c3 = (uint32_t)now();
+      ws.t_solve += c3 - c5;
+    }
+  }
+  if (lead) ws.flush(ctl);
+}
+
+}  // namespace iwpp

@@ -97,6 +97,20 @@ hipError_t launch_frame_marker(int dtype, void* out, const void* img, int64_t H,
                                int64_t ld, hipStream_t st);
 int persistent_blocks_per_cu(const Variant& v);
 
+// Distance transform (iwpp_edt.hip).  Its variants use dtype kDtypeEdt.
+constexpr int kDtypeEdt = 2;
+bool edt_variant_supported(int conn, int tile_h);
+hipError_t launch_persistent_edt(int conn, int tile_h, const DevImage& one, const KParams& kp,
+                                 DevCtl* ctl, int* queue, uint32_t* state, uint8_t* visited,
+                                 int grid, hipStream_t st);
+int persistent_edt_blocks_per_cu(int conn, int tile_h);
+// sites <- own position (background, image value 0) or none (object)
+hipError_t launch_edt_init(void* sites, int64_t ld_out, const void* img, int64_t ld_img,
+                           int64_t H, int64_t W, hipStream_t st);
+// dist <- squared distance of each pixel to its site (-1: none)
+hipError_t launch_edt_dist(void* dist, const void* sites, int64_t ld_out, int64_t H, int64_t W,
+                           hipStream_t st);
+
 constexpr int kTileW = 64;    // one lane per tile column
 constexpr int kThreads = 64;  // one wavefront per workgroup, one tile per wavefront
 

@@ -117,3 +117,67 @@ def fill_holes_by_levels(image: np.ndarray, conn: int) -> np.ndarray:
         filled = ndimage.binary_fill_holes(image >= t, structure=st)
         out[filled] = np.maximum(out[filled], int(t))
     return out.astype(image.dtype)
+
+
+# ------------------------------------------------------------ distance transform
+
+
+def edt_exact_sq(img: np.ndarray) -> np.ndarray:
+    """Exact squared Euclidean distance of every pixel to the nearest
+    background (0) pixel, from ``scipy.ndimage.distance_transform_edt``
+    (rounded: squared distances between pixel centres are integers); -1
+    where the image has no background pixel."""
+    if not (img == 0).any():
+        return np.full(img.shape, -1, np.int64)
+    d = ndimage.distance_transform_edt(img != 0)
+    return np.rint(d.astype(np.float64) ** 2).astype(np.int64)
+
+
+def edt_brute_sq(img: np.ndarray) -> np.ndarray:
+    """The same by brute force over all background pixels (tiny images)."""
+    ys, xs = np.nonzero(img == 0)
+    H, W = img.shape
+    if ys.size == 0:
+        return np.full((H, W), -1, np.int64)
+    yy, xx = np.mgrid[0:H, 0:W]
+    d = (yy[..., None] - ys) ** 2 + (xx[..., None] - xs) ** 2
+    return d.min(axis=-1).astype(np.int64)
+
+
+def decode_sites(sites: np.ndarray):
+    s = sites.astype(np.int64) & 0xFFFFFFFF
+    return s >> 16, s & 0xFFFF
+
+
+def edt_check_valid(img: np.ndarray, sites: np.ndarray, dist2: np.ndarray, conn: int) -> None:
+    """Raise AssertionError unless (sites, dist2) is a valid end state of the
+    site propagation: every site is a background pixel, dist2 is the squared
+    distance to it, background pixels are their own sites, and no pixel has
+    a neighbour holding a strictly closer site (the propagation stopped)."""
+    H, W = img.shape
+    none = sites == -1
+    assert (none == (dist2 == -1)).all(), "sites and distances disagree on 'no site'"
+    if (img == 0).any():
+        assert not none.any(), "a pixel has no site although the image has background"
+    else:
+        assert none.all()
+        return
+    sy, sx = decode_sites(sites)
+    assert (sy < H).all() and (sx < W).all(), "site outside the image"
+    assert (img[sy, sx] == 0).all(), "a site is not a background pixel"
+    yy, xx = np.mgrid[0:H, 0:W]
+    np.testing.assert_array_equal(dist2, (yy - sy) ** 2 + (xx - sx) ** 2)
+    bg = img == 0
+    assert (dist2[bg] == 0).all(), "a background pixel is not its own site"
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if (dy, dx) == (0, 0) or (conn == 4 and dy and dx):
+                continue
+            # q = (y, x), p = (y + dy, x + dx): d(q, site(p)) >= d(q, site(q))
+            y0, y1 = max(0, -dy), H - max(0, dy)
+            x0, x1 = max(0, -dx), W - max(0, dx)
+            qy, qx = yy[y0:y1, x0:x1], xx[y0:y1, x0:x1]
+            psy = sy[y0 + dy:y1 + dy, x0 + dx:x1 + dx]
+            psx = sx[y0 + dy:y1 + dy, x0 + dx:x1 + dx]
+            offered = (qy - psy) ** 2 + (qx - psx) ** 2
+            assert (offered >= dist2[y0:y1, x0:x1]).all(), "propagation had not stopped"
