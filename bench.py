@@ -16,6 +16,10 @@ Workloads (--workload):
          (HIP graph) vs the per-image loop
   c5     served stream: Poisson arrivals at 2000 req/s into the
          continuous-batching server
+  edt    Euclidean distance transform (IWPP site propagation) of the 4096x4096
+         tissue image: distance of every pixel outside the ellipses to the
+         nearest ellipse pixel (ellipse pixels, value > 50, are background)
+  edt32k the same on the 32768x32768 ellipse image of c3u8
 
 Operation (--op, single-image workloads):
   dilate  reconstruction by dilation of the workload (default)
@@ -24,10 +28,10 @@ Operation (--op, single-image workloads):
   fill    fill holes of the workload's mask (frame-marker kernel plus the
           reconstruction by erosion, both inside the timed region)
 
-Parameters: unless --autotune off, the library's autotuner (iwpp_autotune)
-times its candidate parameter sets on the resident workload before the timed
-steps; the chosen set is reported in config.params.  Explicit flags override
-it.
+Parameters: the library defaults, except for c4 (and any workload run with
+--autotune on), where the library's autotuner (iwpp_autotune) first times its
+candidate parameter sets on the resident workload, outside the timed steps;
+the set used is reported in config.params.  Explicit flags override both.
 
 Extras in the JSON line:
   roofline      for the dominant kernel (the persistent tile kernel):
@@ -55,7 +59,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s reconstruction (bit-exact) + % HBM roofline; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1605_00930_amd", "csrc", "iwpp_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1605_00930_amd", "csrc", f)
+               for f in ("iwpp_kernels.hip", "iwpp_edt.hip", "iwpp_device.h", "iwpp_internal.h")]
 
 
 def log(msg: str) -> None:
@@ -63,8 +68,12 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (first 16 hex digits) over the device sources, in order."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str):
@@ -104,6 +113,69 @@ def make_workload(name: str, scale: int = 1):
     raise ValueError(name)
 
 
+def edt_image(name: str, scale: int = 1):
+    """Binary image for the distance-transform workloads (0 = background =
+    ellipse pixels)."""
+    import synth
+
+    if name == "edt":
+        I, _ = synth.c2()
+    else:
+        n = 32768 // scale
+        I, _ = synth.c3_u8(H=n, W=n)
+    return np.where(I > 50, 0, 1).astype(np.uint8)
+
+
+def bench_edt(args, torch, iwpp):
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    img = edt_image(args.workload, args.scale)
+    log("generated %s in %.1f s" % (args.workload, time.perf_counter() - t0))
+    H, W = img.shape
+    it = torch.from_numpy(img).to(dev)
+    del img
+    sites = torch.empty((H, W), dtype=torch.int32, device=dev)
+    dist2 = torch.empty_like(sites)
+    stream = torch.cuda.Stream()
+    params = {"timing": 1}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    call_ms, kern_ms, stats = [], [], None
+    torch.cuda.synchronize()
+    for step in range(args.warmup + args.steps):
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            iwpp.edt_async(it, 8, sites=sites, dist2=dist2, params=params, stream=stream)
+            ev1.record(stream)
+        st = iwpp.stream_status(stream)
+        log("step %d: %.3f ms (kernel %.3f ms, visits %d)"
+            % (step, ev0.elapsed_time(ev1), st["kernel_ms"], st["tile_visits"]))
+        if step >= args.warmup:
+            call_ms.append(ev0.elapsed_time(ev1))
+            kern_ms.append(st["kernel_ms"])
+            stats = st
+    ms = float(np.mean(call_ms))
+    kms = float(np.mean(kern_ms))
+    px = H * W
+    achieved = 8 * px / (kms * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "op": "edt", "H": H, "W": W, "conn": 8,
+                   "desc": "distance to the nearest ellipse pixel (uint8 in, int32 sites and "
+                           "squared distances out)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_persistent_edt (tile worker)",
+                     "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": 8 * px},
+        "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds", "idle_ms",
+                                             "load_ms", "solve_ms", "store_ms", "sync_ms")},
+        "ms_min": round(float(np.min(call_ms)), 4), "ms_cv": round(float(np.std(call_ms) / ms), 4),
+    }
+
+
 def cpu_baseline(name: str, budget_s: float = 20.0, op: str = "dilate"):
     """Time the oracle (single thread) on a bounded sample of the workload."""
     import oracle
@@ -124,6 +196,20 @@ def cpu_baseline(name: str, budget_s: float = 20.0, op: str = "dilate"):
     elif name in ("c4", "c5"):
         pairs = synth.c4(n=24)
         sample = "first 24 images of the batch recipe"
+    elif name in ("edt", "edt32k"):
+        img = edt_image("edt")
+        px = t = 0.0
+        runs = 0
+        while t < budget_s and runs < 10:
+            t0 = time.perf_counter()
+            rc, _, _ = oracle.edt(img, 8)
+            t += time.perf_counter() - t0
+            assert rc == 0
+            px += img.size
+            runs += 1
+        return {"value": round(px / t / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+                "kind": "oracle", "sample": "4096x4096 image of the edt recipe, %d run(s), "
+                                            "%.1f s of CPU time" % (runs, t)}
     else:
         raise ValueError(name)
     px = 0
@@ -165,7 +251,7 @@ def bench_single(args, torch, iwpp):
     params = {"timing": 1}
     tuned = None
     # the tuner times reconstructions by dilation: it runs for --op dilate
-    if args.autotune == "on" or (args.autotune == "auto" and args.op == "dilate"):
+    if args.autotune == "on" and args.op == "dilate":
         t0 = time.perf_counter()
         tuned = {k: v for k, v in iwpp.autotune(Jt0, It, 8, stream=stream).items() if v}
         log("autotuned in %.1f s: %s" % (time.perf_counter() - t0, tuned))
@@ -425,7 +511,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3u8", "c3i32", "c4", "c5"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c3u8", "c3i32", "c4", "c5", "edt", "edt32k"])
     ap.add_argument("--scale", type=int, default=1, help="divide the 32K side (c3*) by this")
     ap.add_argument("--op", default="dilate", choices=["dilate", "erode", "fill"],
                     help="single-image workloads: which operation to time")
@@ -437,7 +524,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="tune parameters on the resident workload before timing, outside the "
-                         "timed region (auto: on for --op dilate and for c4)")
+                         "timed region (auto: on for c4 only, whose recipe asks for it)")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="c5 seconds of arrivals")
     ap.add_argument("--pool", type=int, default=64, help="c5 distinct requests")
@@ -448,7 +535,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run the library copy kernel on this many MiB (profiler scaling)")
     args = ap.parse_args()
-    if args.op != "dilate" and args.workload in ("c4", "c5"):
+    if args.op != "dilate" and args.workload in ("c4", "c5", "edt", "edt32k"):
         ap.error("--op applies to single-image workloads only")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
@@ -482,6 +569,8 @@ def main():
         res = bench_batched(args, torch, iwpp)
     elif args.workload == "c5":
         res = bench_served(args, torch, iwpp)
+    elif args.workload in ("edt", "edt32k"):
+        res = bench_edt(args, torch, iwpp)
     else:
         res = bench_single(args, torch, iwpp)
     if not args.no_cpu_baseline:

@@ -123,7 +123,8 @@ typedef struct iwpp_stats {
  *                 reports their device time.
  *   seed_queue    a re-visited tile whose new halo can raise at most this
  *                 many border pixels goes straight to its queue; more start
- *                 with a scan round (0 = default 32, -1 = always scan).
+ *                 with a scan round (0 = default: always scan for uint8, 8
+ *                 for int32; -1 = always scan).
  *   queue_waves   a tile queue that still holds receivers after this many
  *                 waves hands the tile to rounds of directional passes and a
  *                 new scan (0 = default 4, -1 = no limit).

@@ -242,6 +242,13 @@ def edt(image, conn: int = 8, *, sites=None, dist2=None, params=None, stream=Non
     """Euclidean distance transform of a uint8 image (0 = background).
     Returns (sites, dist2, counters): int32 tensors of nearest-site positions
     packed (y << 16) | x and squared distances (-1 where there is no site)."""
+    sites, dist2 = edt_async(image, conn, sites=sites, dist2=dist2, params=params,
+                             stream=stream)
+    return sites, dist2, stream_status(stream, check=check)
+
+
+def edt_async(image, conn: int = 8, *, sites=None, dist2=None, params=None, stream=None):
+    """Queue the distance transform on `stream`; returns (sites, dist2)."""
     import torch
 
     if image.dim() != 2 or image.dtype != torch.uint8 or not image.is_cuda:
@@ -263,7 +270,7 @@ def edt(image, conn: int = 8, *, sites=None, dist2=None, params=None, stream=Non
                                 _ptr(_params(params)), _stream_handle(stream))
     if rc != OK:
         raise IwppError(rc, "iwpp_edt_async")
-    return sites, dist2, stream_status(stream, check=check)
+    return sites, dist2
 
 
 def reconstruct_batched(pairs, conn: int = 8, *, clamp: bool = False, erosion: bool = False,

@@ -109,7 +109,9 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   base.tile_h = default_tile_h(dtype);
   base.sweeps = dtype == IWPP_U8 ? 4 : 1;
   base.mode = 0;
-  base.seed_queue = 32;
+  // uint8: fill-holes fronts wind through whole tiles, so re-visits go
+  // straight to rounds of passes; int32 (h-dome): short fronts, few seeds
+  base.seed_queue = dtype == IWPP_U8 ? -1 : 8;
   base.queue_waves = 4;
   {
     std::lock_guard<std::mutex> g(g_mu);
