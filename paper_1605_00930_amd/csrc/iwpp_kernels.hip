@@ -430,18 +430,41 @@ struct Tile {
       wsync();
     }
   }
-  __device__ static bool sweep_round(L& s, VisitStats& vs) {
+  // Pass p of a round (0 down, 1 up, 2 right, 3 left); true if it changed a
+  // pixel.  The rows it changed are marked in rowdirty.
+  __device__ static bool run_pass(L& s, int p) {
     uint64_t d0 = 0, d1 = 0;
-    pass_vert<+1>(s, d0, d1);
-    wsync();
-    pass_vert<-1>(s, d0, d1);
-    wsync();
-    pass_horz<+1>(s, d0, d1);
-    pass_horz<-1>(s, d0, d1);
-    vs.rounds++;
+    if (p == 0) {
+      pass_vert<+1>(s, d0, d1);
+      wsync();
+    } else if (p == 1) {
+      pass_vert<-1>(s, d0, d1);
+      wsync();
+    } else if (p == 2) {
+      pass_horz<+1>(s, d0, d1);
+    } else {
+      pass_horz<-1>(s, d0, d1);
+    }
     for (int y = lane(); y < TH; y += 64)
       if ((y < 64 ? (d0 >> y) : (d1 >> (y - 64))) & 1ull) s.rowdirty[y] = 1;
     return (d0 | d1) != 0;
+  }
+
+  // Up to `budget` rounds of passes.  A pass that changes nothing leaves the
+  // tile as it was, so four passes in a row that change nothing (one per
+  // direction, in any cyclic order) all saw the same tile: it is then at a
+  // fixed point for its halo, and this returns true without running the
+  // rest of the round and a whole confirming round.
+  __device__ static bool sweep_rounds(L& s, int budget, VisitStats& vs) {
+    int quiet = 0, k = 0;
+    for (; k < 4 * budget && quiet < 4; ++k) {
+      if (run_pass(s, k & 3))
+        quiet = 0;
+      else
+        ++quiet;
+    }
+    vs.rounds += (uint32_t)((k + 3) / 4);
+    return quiet >= 4;
   }
 
   // ---------------------------------------------------------- seeds
@@ -623,12 +646,7 @@ struct Tile {
       if (budget < 1) budget = 1;
     }
     for (uint32_t guard = 0;; ++guard) {
-      bool ch = true;
-      for (int r = 0; r < budget && ch; ++r) {
-        ch = sweep_round(s, vs);
-        wsync();
-      }
-      if (!ch) return;  // a round that changed nothing: fixed point
+      if (sweep_rounds(s, budget, vs)) return;  // fixed point
       const int n = scan_receivers(s);
       if (n == 0) return;
       if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
