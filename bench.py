@@ -256,7 +256,7 @@ def bench_single(args, torch, iwpp):
         tuned = {k: v for k, v in iwpp.autotune(Jt0, It, 8, stream=stream).items() if v}
         log("autotuned in %.1f s: %s" % (time.perf_counter() - t0, tuned))
         params.update(tuned)
-    for k in ("tile_h", "sweeps", "mode", "seed_queue", "queue_waves"):
+    for k in ("tile_h", "sweeps", "mode", "seed_queue", "queue_waves", "bands"):
         v = getattr(args, k)
         if v is not None:
             params[k] = v
@@ -521,6 +521,7 @@ def main():
     ap.add_argument("--mode", type=int, default=None)
     ap.add_argument("--seed-queue", dest="seed_queue", type=int, default=None)
     ap.add_argument("--queue-waves", dest="queue_waves", type=int, default=None)
+    ap.add_argument("--bands", type=int, default=None, help="gray-level classes (mode 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="tune parameters on the resident workload before timing, outside the "

@@ -112,7 +112,17 @@ typedef struct iwpp_stats {
  *   sweeps        rounds of directional passes before switching a tile to its
  *                 queue (>= 0; -1 selects 0 explicitly).
  *   mode          0 persistent kernel with a global tile queue (default);
- *                 1 host-driven rounds (one launch per round, for comparison).
+ *                 1 host-driven rounds (one launch per round, for comparison);
+ *                 2 gray-level bands: the priority ordering of the paper's
+ *                 "Uso de Diferentes Estruturas de Dados" at the granularity
+ *                 of tiles and bands of values.  The marker's value range is
+ *                 split into `bands` classes; a sequence of persistent
+ *                 launches handles the classes from the highest down, each
+ *                 queueing only the tile activations whose value lies in or
+ *                 above its class and deferring the others to a later
+ *                 launch.  Single images only (batched calls return
+ *                 IWPP_E_UNSUPPORTED); one extra pass reads the marker for
+ *                 its range, and the host waits once per launch.
  *   grid          persistent workgroups (0 = fill the device).
  *   max_tile_visits  stop after this many tile visits (0 = no limit); used to
  *                 test restart: the call then returns IWPP_E_INCOMPLETE.
@@ -128,6 +138,7 @@ typedef struct iwpp_stats {
  *   queue_waves   a tile queue that still holds receivers after this many
  *                 waves hands the tile to rounds of directional passes and a
  *                 new scan (0 = default 4, -1 = no limit).
+ *   bands         mode 2: number of gray-level classes (0 = default 16).
  */
 typedef struct iwpp_params {
   int32_t tile_h;
@@ -140,6 +151,7 @@ typedef struct iwpp_params {
   int32_t timing;
   int32_t seed_queue;
   int32_t queue_waves;
+  int32_t bands;
 } iwpp_params;
 
 /* Library version, e.g. 10000 for 1.0.0. */

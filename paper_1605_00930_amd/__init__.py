@@ -69,7 +69,8 @@ class Params(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("max_tile_visits", ctypes.c_int64), ("order_seed", ctypes.c_uint32),
                 ("spin_limit", ctypes.c_uint32), ("timing", ctypes.c_int32),
-                ("seed_queue", ctypes.c_int32), ("queue_waves", ctypes.c_int32)]
+                ("seed_queue", ctypes.c_int32), ("queue_waves", ctypes.c_int32),
+                ("bands", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -134,12 +135,14 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   r.spin_limit = 1u << 24;
   r.timing = 0;
   r.seed_queue_max = base.seed_queue < 0 ? 0 : base.seed_queue;
+  r.bands = 16;
   r.queue_waves = base.queue_waves < 0 ? UINT32_MAX : (uint32_t)base.queue_waves;
   if (user) {
     r.timing = user->timing;
     if (user->seed_queue) r.seed_queue_max = user->seed_queue < 0 ? 0 : user->seed_queue;
     if (user->queue_waves)
       r.queue_waves = user->queue_waves < 0 ? UINT32_MAX : (uint32_t)user->queue_waves;
+    if (user->bands) r.bands = user->bands;
     if (user->tile_h) r.tile_h = user->tile_h;
     if (user->sweeps) r.sweeps = user->sweeps < 0 ? 0 : user->sweeps;
     if (user->mode) r.mode = user->mode;
@@ -156,7 +159,8 @@ int check_params(const iwpp_params* p) {
   if (p->tile_h != 0 && p->tile_h != 32 && p->tile_h != 64 && p->tile_h != 128)
     return IWPP_E_ARG;
   if (p->sweeps < -1 || p->sweeps > 64) return IWPP_E_ARG;
-  if (p->mode != 0 && p->mode != 1) return IWPP_E_ARG;
+  if (p->mode < 0 || p->mode > 2) return IWPP_E_ARG;
+  if (p->bands < 0 || p->bands > 4096) return IWPP_E_ARG;
   if (p->grid < 0 || p->max_tile_visits < 0) return IWPP_E_ARG;
   return IWPP_OK;
 }
@@ -311,7 +315,31 @@ int Buffers::ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds) {
   return IWPP_OK;
 }
 
+int Buffers::ensure_bands(int64_t ntiles) {
+  if (ntiles <= band_cap) return IWPP_OK;
+  (void)hipStreamSynchronize(stream_owner);
+  (void)hipFree(dclass);
+  (void)hipFree(listed);
+  (void)hipFree(list[0]);
+  (void)hipFree(list[1]);
+  dclass = nullptr;
+  listed = nullptr;
+  list[0] = list[1] = nullptr;
+  const int64_t cap = std::max<int64_t>(ntiles, 1024);
+  HIP_TRY(hipMalloc(&dclass, cap * sizeof(int)));
+  HIP_TRY(hipMalloc(&listed, cap * sizeof(uint32_t)));
+  HIP_TRY(hipMalloc(&list[0], cap * sizeof(int)));
+  HIP_TRY(hipMalloc(&list[1], cap * sizeof(int)));
+  if (!minmax) HIP_TRY(hipMalloc(&minmax, 2 * sizeof(int)));
+  band_cap = cap;
+  return IWPP_OK;
+}
 void Buffers::release() {
+  (void)hipFree(dclass);
+  (void)hipFree(listed);
+  (void)hipFree(list[0]);
+  (void)hipFree(list[1]);
+  (void)hipFree(minmax);
   if (ev[0]) (void)hipEventDestroy(ev[0]);
   if (ev[1]) (void)hipEventDestroy(ev[1]);
   (void)hipFree(ctl);
@@ -343,6 +371,99 @@ int plan_queues(const Variant& v, const Resolved& rp, int64_t ntiles, int nimg,
 // Enqueue one reconstruction of `nimg` images (descriptors either `one` or a
 // device array `d_imgs`) on `st`, using buffers `b`.  The control block is
 // copied to b.host_ctl at the end (stream-ordered).
+// Gray-level bands (mode 2): a sequence of persistent launches over
+// decreasing classes of values (the priority ordering of "Uso de Diferentes
+// Estruturas de Dados", by bands of gray levels).  A launch queues only the
+// activations whose class is at or above its band and lists the other tiles
+// for a later launch; the next launch starts from that list at the highest
+// class deferred.  Classes only decrease, so the sequence ends.
+int enqueue_bands(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& one,
+                  const DevImage* d_imgs, int nimg, int64_t ntiles, hipStream_t st, KParams kp,
+                  int64_t* launches) {
+  if (nimg != 1 || d_imgs) return IWPP_E_UNSUPPORTED;
+  int grid = 0;
+  int rc = plan_queues(v, rp, ntiles, nimg, one, &grid, &kp);
+  if (rc) return rc;
+  rc = b.ensure(ntiles, kp.qcap * (uint32_t)kp.nq, nimg, false);
+  if (!rc) rc = b.ensure_bands(ntiles);
+  if (rc) return rc;
+  order_for(rp.order_seed, ntiles, &kp.order_mul, &kp.order_add);
+  // value range of the marker, in the tile order
+  int* mm = (int*)b.host_ctl;  // the pinned control copy serves as staging
+  mm[0] = INT_MAX;
+  mm[1] = INT_MIN;
+  HIP_TRY(hipMemcpyAsync(b.minmax, mm, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_minmax(v.dtype, one.J, one.H, one.W, one.ld, rp.flip, b.minmax, st));
+  HIP_TRY(hipMemcpyAsync(mm, b.minmax, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t vmin = mm[0], range = (int64_t)mm[1] - mm[0];
+  const int nb = rp.bands > 0 ? rp.bands : 16;
+  uint32_t shift = 0;
+  while ((range >> shift) >= nb) ++shift;
+  kp.band_base = (int32_t)vmin;
+  kp.band_shift = shift;
+  kp.band = (int32_t)(range >> shift);  // the top class: the first launch visits every tile
+  kp.dclass = b.dclass;
+  kp.listed = b.listed;
+  kp.list_mode = 0;
+  kp.list_len = 0;
+  kp.list_in = nullptr;
+  kp.list_out = b.list[0];
+  DevCtl sum{};
+  int status = 0;
+  int64_t nl = 0;
+  b.timed = false;
+  b.rounds_ms = 0;
+  if (rp.timing) {
+    if (!b.ev[0]) HIP_TRY(hipEventCreate(&b.ev[0]));
+    if (!b.ev[1]) HIP_TRY(hipEventCreate(&b.ev[1]));
+  }
+  for (int cur = 0;;) {
+    HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, st));
+    if (kp.list_mode) HIP_TRY(launch_list_mark(kp, b.state, st));
+    if (rp.timing) HIP_TRY(hipEventRecord(b.ev[0], st));
+    HIP_TRY(launch_persistent(v, one, d_imgs, kp, b.ctl, b.queue, b.state, b.visited, grid, st));
+    if (rp.timing) HIP_TRY(hipEventRecord(b.ev[1], st));
+    nl += kp.list_mode ? 3 : 2;
+    HIP_TRY(hipMemcpyAsync(b.host_ctl, b.ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (rp.timing) {
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, b.ev[0], b.ev[1]));
+      b.rounds_ms += ms;
+    }
+    const DevCtl& c = *b.host_ctl;
+    sum.visits += c.visits;
+    sum.sweeps += c.sweeps;
+    sum.pushes += c.pushes;
+    sum.overflows += c.overflows;
+    sum.reproc += c.reproc;
+    sum.requeued += c.requeued;
+    sum.qiters += c.qiters;
+    sum.t_idle += c.t_idle;
+    sum.t_load += c.t_load;
+    sum.t_solve += c.t_solve;
+    sum.t_store += c.t_store;
+    sum.t_sync += c.t_sync;
+    status |= (int)c.status.v;
+    const uint32_t next = c.next_len.v;
+    const int maxd = (int)c.max_deferred.v;
+    if ((status & (ST_INTERNAL | ST_INCOMPLETE | ST_ABORT)) || next == 0 || maxd < 0) break;
+    // next launch: the list just written, at the highest class deferred
+    kp.band = maxd;
+    kp.list_mode = 1;
+    kp.list_in = b.list[cur];
+    kp.list_len = next;
+    cur ^= 1;
+    kp.list_out = b.list[cur];
+  }
+  // the totals of all launches stand in the host copy for status and stats
+  sum.status.v = (uint32_t)status;
+  *b.host_ctl = sum;
+  if (launches) *launches = nl + 1;
+  return IWPP_OK;
+}
+
 int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& one,
             const DevImage* d_imgs, int nimg, int64_t ntiles, hipStream_t st, int64_t* launches) {
   KParams kp{};
@@ -354,7 +475,9 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
   kp.seed_queue_max = rp.seed_queue_max;
   kp.queue_waves = rp.queue_waves;
   kp.flip = rp.flip;
+  kp.band = -1;
   int64_t nl = 0;
+  if (rp.mode == 2) return enqueue_bands(b, v, rp, one, d_imgs, nimg, ntiles, st, kp, launches);
   if (rp.mode == 0) {
     int grid = 0;
     int rc = plan_queues(v, rp, ntiles, nimg, one, &grid, &kp);

@@ -142,6 +142,8 @@ __device__ __forceinline__ int queue_of(const KParams& kp, int64_t t) {
 
 // Number of tiles of queue q's first pass: chunks q, q + nq, ...
 __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
+  // list mode: entry i of the list belongs to queue i % nq
+  if (kp.list_mode) return q < kp.list_len ? (kp.list_len - 1 - q) / kp.nq + 1 : 0;
   const int64_t nchunks = (kp.ntiles + kp.chunk - 1) / kp.chunk;
   if (q >= nchunks) return 0;
   const int64_t nc = (nchunks - 1 - q) / kp.nq + 1;
@@ -151,6 +153,7 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
 }
 
 __device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, int q, int64_t i) {
+  if (kp.list_mode) return kp.list_in[i * kp.nq + q];
   const int64_t c = (i / kp.chunk) * kp.nq + q;
   const int64_t t = c * kp.chunk + i % kp.chunk;
   if (kp.order_mul == 1 && kp.order_add == 0) return t;
@@ -207,10 +210,11 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 // the XCD, which a waiting worker must not do to the tiles others are
 // working on.
 static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                              int grid, uint32_t h) {
+                              int grid, uint32_t h, bool& first_pass) {
   const int64_t len = first_pass_len(kp, q);
   int v;
-  if ((int64_t)h < len) {
+  first_pass = (int64_t)h < len;
+  if (first_pass) {
     v = (int)first_pass_tile(kp, q, h);
   } else {
     int* slot = ring_slot(queue, kp, q, h, len);
@@ -249,12 +253,24 @@ constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
 static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                         int grid, uint32_t pre) {
+                         int grid, uint32_t pre, bool& first_pass) {
+  first_pass = false;
   if (pre == kNoTicket) {
     if (ld_rlx_u32(&ctl->done.v)) return -1;
     pre = atomicAdd(&ctl->head[q].v, 1u);
   }
-  return resolve_ticket(ctl, queue, kp, state, q, grid, pre);
+  return resolve_ticket(ctl, queue, kp, state, q, grid, pre, first_pass);
+}
+
+// Gray-level bands: remember that tile t has work of class c for a later
+// launch (one lane; its class is already recorded).  The tile enters the
+// next launch's list once.
+static __device__ void defer_tile(DevCtl* ctl, const KParams& kp, int t, int c) {
+  if (atomicExch(&kp.listed[t], 1u) == 0u) {
+    const uint32_t i = atomicAdd(&ctl->next_len.v, 1u);
+    __hip_atomic_store(&kp.list_out[i], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  atomicMax((int*)&ctl->max_deferred.v, c);
 }
 
 // While queue q's first pass lasts, the next ticket is taken before the
@@ -275,7 +291,7 @@ static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q
 // always already counted.  Returns 1 if t must be run again (a neighbour
 // asked while it ran), 2 if this visit completed the launch, 0 otherwise.
 static __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
-                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act,
+                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
                        WorkerStats& ws) {
   const int d = threadIdx.x;
   int n = -1;
@@ -286,9 +302,17 @@ static __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32
   }
   bool fresh = false;  // was idle: this wavefront enqueues it
   bool released = false;
-  if (n >= 0)
-    fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  if (n >= 0) {
+    // with bands every request records its class on the tile, so that a
+    // listed tile whose first-pass visit is still ahead knows it has work
+    // at this band; below the band a later launch takes it
+    if (kp.band >= 0) atomicMax(&kp.dclass[n], cls);
+    if (kp.band >= 0 && cls < kp.band)
+      defer_tile(ctl, kp, n, cls);
+    else
+      fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  }
   if (d == 9) {
     uint32_t expect = TS_RUNNING;
     released = __hip_atomic_compare_exchange_strong(
@@ -344,21 +368,44 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
   uint32_t pre = kNoTicket;  // lane 0: a ticket taken ahead of time
   for (;;) {
     uint32_t c0 = (uint32_t)now();
-    int t = 0;
+    int t = 0, fp = 0;
     if (lead) {
-      t = queue_pop(ctl, queue, kp, state, q, grid, pre);
+      bool first_pass = false;
+      t = queue_pop(ctl, queue, kp, state, q, grid, pre, first_pass);
+      fp = first_pass ? 1 : 0;
       pre = kNoTicket;
     }
     t = __builtin_amdgcn_readfirstlane(t);
+    fp = __builtin_amdgcn_readfirstlane(fp);
     uint32_t c1 = (uint32_t)now();
     ws.t_idle += c1 - c0;
     if (t < 0) break;
-    ws.visits++;
     const int k = imgs ? find_image(imgs, kp.nimg, t) : 0;
     const DevImage im = imgs ? imgs[k] : one;
     const int64_t tl = (int64_t)t - im.tile_base;
     const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
     const int64_t y0 = ty * TH, x0 = tx * TW;
+    if (kp.band >= 0) {
+      // gray-level bands: this visit takes the tile's deferred work (the
+      // halo it loads holds it).  A list entry with nothing at or above the
+      // band goes back to the next launch's list without a visit.
+      int dc = -1;
+      if (lead)
+        dc = __hip_atomic_exchange(&kp.dclass[t], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dc = __builtin_amdgcn_readfirstlane(dc);
+      if (kp.list_mode && fp && dc < kp.band) {
+        if (lead && dc >= 0) {
+          atomicMax(&kp.dclass[t], dc);
+          defer_tile(ctl, kp, t, dc);
+        }
+        drain_memory();
+        const int res = publish(ctl, queue, kp, state, t, im, ty, tx, 0u, 0, ws);
+        if (res == 2) stop_all(ctl, queue, kp, grid);
+        if (res != 1) continue;
+        ws.visits--;  // a neighbour asked for the tile meanwhile: visit it after all
+      }
+    }
+    ws.visits++;
     const bool first = ld_coherent(&visited[t]) == 0;
     VisitStats vs;
     bool hit = false;
@@ -372,7 +419,13 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     ws.t_solve += c3 - c2;
     for (;;) {
       TP::store(s, im, y0, x0, kp.flip);
-      const uint32_t act = TP::activation_mask(s, y0, x0);
+      int amax = 0;
+      const uint32_t act = TP::activation_mask(s, y0, x0, amax);
+      int cls = 0;
+      if (kp.band >= 0) {
+        cls = (amax - kp.band_base) >> kp.band_shift;
+        if (cls < 0) cls = 0;
+      }
       uint32_t c3b = (uint32_t)now();
       ws.t_store += c3b - c3;
       ws.add(vs);
@@ -383,7 +436,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       }
       // the write-back is complete before anyone is told about it
       drain_memory();
-      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, ws);
+      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, cls, ws);
       if (res == 2) stop_all(ctl, queue, kp, grid);
       uint32_t c4 = (uint32_t)now();
       ws.t_sync += c4 - c3b;

@@ -275,18 +275,19 @@ struct EdtTile {
     d0 |= __ballot(live && dirty);
   }
 
-  // One round of the four passes; true if any pixel changed.
-  __device__ static bool sweep_round(L& s, int64_t y0, int64_t x0, VisitStats& vs) {
+  // Pass p of a round (0 down, 1 up, 2 right, 3 left); true if it changed
+  // a pixel.  The rows it changed are marked in rowdirty.
+  __device__ static bool run_pass(L& s, int64_t y0, int64_t x0, int p) {
     uint64_t d0 = 0;
-    pass_vert<+1>(s, y0, x0, d0);
+    if (p == 0)
+      pass_vert<+1>(s, y0, x0, d0);
+    else if (p == 1)
+      pass_vert<-1>(s, y0, x0, d0);
+    else if (p == 2)
+      pass_horz<+1>(s, y0, x0, d0);
+    else
+      pass_horz<-1>(s, y0, x0, d0);
     wsync();
-    pass_vert<-1>(s, y0, x0, d0);
-    wsync();
-    pass_horz<+1>(s, y0, x0, d0);
-    wsync();
-    pass_horz<-1>(s, y0, x0, d0);
-    wsync();
-    vs.rounds++;
     for (int y = lane(); y < TH; y += 64)
       if ((d0 >> y) & 1ull) s.rowdirty[y] = 1;
     return d0 != 0;
@@ -297,9 +298,16 @@ struct EdtTile {
   // queue parameters do not apply).
   __device__ static void solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
                                uint32_t iter_limit, VisitStats& vs, bool& hit_limit) {
-    for (uint32_t r = 0;; ++r) {
-      if (!sweep_round(s, y0, x0, vs)) return;
-      if (r >= iter_limit) {
+    // passes down, up, right, left, round after round, until four in a row
+    // change nothing: those four saw the same tile in every direction
+    int quiet = 0;
+    for (uint32_t k = 0; quiet < 4; ++k) {
+      if (run_pass(s, y0, x0, (int)(k & 3u)))
+        quiet = 0;
+      else
+        ++quiet;
+      if ((k & 3u) == 3u) vs.rounds++;
+      if (k >= 4u * iter_limit) {
         hit_limit = true;
         return;
       }
@@ -323,7 +331,8 @@ struct EdtTile {
       x = TW - 1;
     }
   }
-  __device__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0) {
+  __device__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0, int& amax) {
+    amax = 0;  // no gray-level bands for distances
     uint32_t m = 0;
     for (int base = 0; base < G::RING; base += 64) {
       const int e = base + lane();

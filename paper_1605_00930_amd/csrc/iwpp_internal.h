@@ -32,6 +32,8 @@ struct DevCtl {
   HotWord status;            // ST_* bits (int32)
   HotWord done;              // set once no more work can arrive
   HotWord visits_cap;        // visit counter, only used with a visit limit
+  HotWord next_len;          // gray-level bands: tiles appended to the next launch's list
+  HotWord max_deferred;      // gray-level bands: highest class deferred (int32, -1 none)
   uint64_t visits;     // tile visits (first visits, re-visits, in-place reprocessing)
   uint64_t sweeps;     // rounds of the four directional passes
   uint64_t pushes;     // entries processed by tile queues
@@ -71,6 +73,18 @@ struct KParams {
   int32_t seed_queue_max;  // re-visits with at most this many halo receivers skip the scans
   uint32_t queue_waves;    // queue waves before a tile falls back to sweep rounds
   uint32_t flip;           // 0: dilation; ~0u: erosion (values complemented in the tile)
+  // Gray-level bands (mode 2): activations whose value class
+  // (value - band_base) >> band_shift is below `band` are deferred to a later
+  // launch instead of being queued.  band < 0: no bands.
+  int32_t band;
+  int32_t band_base;
+  uint32_t band_shift;
+  int32_t list_mode;       // the first pass is list_in[0 .. list_len) (else all tiles)
+  int64_t list_len;
+  const int* list_in;
+  int* list_out;           // tiles with deferred work for the next launch
+  int* dclass;             // per tile: highest deferred class, -1 none
+  uint32_t* listed;        // per tile: already in list_out
   int32_t nq;           // tile queues in use (1..kMaxQueues)
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
@@ -92,6 +106,11 @@ hipError_t launch_round(const Variant& v, const DevImage& one, const DevImage* i
                         uint8_t* visited, hipStream_t st);
 hipError_t launch_clear_round(DevCtl* ctl, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// Gray-level bands: mark the tiles of kp.list_in pending; min / max of the
+// marker (tile order) into out[0], out[1] (which the caller initialises).
+hipError_t launch_list_mark(const KParams& kp, uint32_t* state, hipStream_t st);
+hipError_t launch_minmax(int dtype, const void* J, int64_t H, int64_t W, int64_t ld,
+                         uint32_t flip, int* out, hipStream_t st);
 // out <- image on the 1-pixel frame, the highest value inside (fill-holes marker).
 hipError_t launch_frame_marker(int dtype, void* out, const void* img, int64_t H, int64_t W,
                                int64_t ld, hipStream_t st);

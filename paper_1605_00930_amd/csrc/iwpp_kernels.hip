@@ -661,8 +661,11 @@ struct Tile {
   // Neighbour tiles (3x3 grid index) that a changed border pixel can
   // propagate into.  Halo values are the ones seen at load time; they never
   // exceed the current ones, so no needed activation is missed.
-  __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t) {
+  // `amax` receives the largest value among the border pixels that activate
+  // a neighbour (the class of the visit's fronts for gray-level bands).
+  __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t, int& amax) {
     uint32_t m = 0;
+    int vmax = LO;
     for (int base = 0; base < G::RING; base += 64) {
       const int e = base + lane();
       if (e >= G::RING) continue;
@@ -687,9 +690,14 @@ struct Tile {
         const int cx = hx < 0 ? 0 : (hx >= TW ? 2 : 1);
         if (cy == 1 && cx == 1) continue;
         const int jh = jv(s, hy, hx);
-        if (j > jh && jh < iv(s, hy, hx)) m |= 1u << (cy * 3 + cx);
+        if (j > jh && jh < iv(s, hy, hx)) {
+          m |= 1u << (cy * 3 + cx);
+          vmax = imax(vmax, j);
+        }
       }
     }
+    for (int off = 32; off > 0; off >>= 1) vmax = imax(vmax, __shfl_xor(vmax, off));
+    amax = __builtin_amdgcn_readfirstlane(vmax);
     // OR across the wavefront
     uint32_t all = 0;
     for (int d = 0; d < 9; ++d)
@@ -732,7 +740,8 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
             vs, hit);
   TP::store(s, im, y0, x0, kp.flip);
-  const uint32_t act = TP::activation_mask(s, y0, x0);
+  int amax = 0;
+  const uint32_t act = TP::activation_mask(s, y0, x0, amax);
   if (threadIdx.x == 0) {
     WorkerStats ws;
     ws.add(vs);
@@ -762,8 +771,17 @@ __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uin
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = gid; i < kp.ntiles; i += stride) {
-    if (state) state[i] = TS_PENDING;
-    visited[i] = 0;
+    // a list launch (gray-level bands after the first) keeps the tile states
+    // (all idle after the previous launch) and the first-visit flags; its
+    // listed tiles are marked pending by k_list_mark
+    if (!kp.list_mode) {
+      if (state) state[i] = TS_PENDING;
+      visited[i] = 0;
+      if (kp.band >= 0) {
+        kp.dclass[i] = -1;
+        kp.listed[i] = 0;
+      }
+    }
     if (active) active[i] = 1;
   }
   if (queue) {
@@ -778,7 +796,44 @@ __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uin
     __syncthreads();
     if (threadIdx.x < kMaxQueues && queue && threadIdx.x < kp.nq)
       ctl->tail[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
-    if (threadIdx.x == 0) ctl->pending.v = state ? (uint32_t)kp.ntiles : 0u;
+    if (threadIdx.x == 0) {
+      ctl->pending.v = state ? (uint32_t)(kp.list_mode ? kp.list_len : kp.ntiles) : 0u;
+      ctl->max_deferred.v = 0xFFFFFFFFu;  // -1: nothing deferred
+    }
+  }
+}
+
+// Gray-level bands: the tiles of this launch's list start pending, and may
+// enter the next launch's list again.
+__global__ void k_list_mark(KParams kp, uint32_t* state) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kp.list_len; i += stride) {
+    const int t = kp.list_in[i];
+    state[t] = TS_PENDING;
+    kp.listed[t] = 0;
+  }
+}
+
+// Smallest and largest marker value in the tile order (after the complement
+// of an erosion), for the class boundaries of gray-level bands.
+template <typename T>
+__global__ __launch_bounds__(256) void k_minmax(const T* __restrict__ J, int64_t H, int64_t W,
+                                                int64_t ld, uint32_t flip, int* out) {
+  int lo = INT_MAX, hi = INT_MIN;
+  for (int64_t y = blockIdx.y; y < H; y += gridDim.y)
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < W;
+         x += (int64_t)gridDim.x * 256) {
+      const int v = (int)(T)(J[y * ld + x] ^ (T)flip);
+      lo = imin(lo, v);
+      hi = imax(hi, v);
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = imin(lo, __shfl_xor(lo, off));
+    hi = imax(hi, __shfl_xor(hi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&out[0], lo);
+    atomicMax(&out[1], hi);
   }
 }
 
@@ -873,6 +928,29 @@ hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* sta
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, st, kp, ctl, queue, state,
                      visited, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_mark(const KParams& kp, uint32_t* state, hipStream_t st) {
+  int64_t blocks = (kp.list_len + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_list_mark, dim3((unsigned)blocks), dim3(256), 0, st, kp, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax(int dtype, const void* J, int64_t H, int64_t W, int64_t ld,
+                         uint32_t flip, int* out, hipStream_t st) {
+  int64_t gx = (W + 255) / 256, gy = H;
+  if (gx > 16) gx = 16;
+  if (gy > 1024) gy = 1024;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_minmax<uint8_t>, grid, dim3(256), 0, st, (const uint8_t*)J, H, W, ld,
+                       flip, out);
+  else
+    hipLaunchKernelGGL(k_minmax<int32_t>, grid, dim3(256), 0, st, (const int32_t*)J, H, W, ld,
+                       flip, out);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ struct Resolved {
   int seed_queue_max;
   uint32_t queue_waves;
   uint32_t flip;  // 0 dilation, ~0u erosion (from IWPP_FLAG_EROSION)
+  int bands;      // mode 2: number of gray-level classes
 };
 
 // Device buffers of one launch context (a stream workspace, a batch plan or a
@@ -44,7 +45,14 @@ struct Buffers {
   hipEvent_t ev[2] = {nullptr, nullptr};  // kernel timing (created on demand)
   bool timed = false;                     // last enqueue recorded ev[0..1]
   double rounds_ms = 0;                   // host-driven rounds: summed kernel time
+  // gray-level bands
+  int* dclass = nullptr;
+  uint32_t* listed = nullptr;
+  int* list[2] = {nullptr, nullptr};
+  int* minmax = nullptr;
+  int64_t band_cap = 0;
   int ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds);
+  int ensure_bands(int64_t ntiles);
   void release();
 };
 

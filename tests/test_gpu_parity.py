@@ -126,6 +126,8 @@ def test_row_pitch(iwpp):
     {"grid": 1}, {"mode": 1, "sweeps": -1}, {"mode": 1, "tile_h": 128}, {"seed_queue": -1},
     {"seed_queue": 100000}, {"seed_queue": 100000, "sweeps": -1}, {"queue_waves": 1},
     {"queue_waves": -1}, {"queue_waves": 2, "seed_queue": 100000, "sweeps": -1},
+    {"mode": 2}, {"mode": 2, "bands": 3}, {"mode": 2, "bands": 300, "sweeps": 1},
+    {"mode": 2, "bands": 64, "seed_queue": 100000, "queue_waves": 2},
 ])
 def test_parameters_do_not_change_the_result(iwpp, params):
     th = params.get("tile_h")
@@ -159,7 +161,7 @@ def test_marker_above_mask(iwpp):
     same(got, expect(I, J, 8, clamp=True), "clamped")
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_restart_from_partial_result(iwpp, mode):
     import torch
 
@@ -262,6 +264,25 @@ def test_erosion_marker_below_mask(iwpp):
     got, st = run(iwpp, I, J, 8, clamp=True, erosion=True)
     assert st["rc"] == iwpp.OK
     same(got, expect_erode(I, J, 8, clamp=True), "erosion clamped")
+
+
+def test_erosion_bands(iwpp):
+    rng = np.random.default_rng(9)
+    for dtype in (np.uint8, np.int32):
+        I, J = synth.random_pair_above(rng, 230, 310, dtype, "uniform", levels=40)
+        announce("erosion gray-level bands %s" % np.dtype(dtype).name)
+        got, _ = run(iwpp, I, J, 8, erosion=True, params={"mode": 2, "bands": 8})
+        same(got, expect_erode(I, J, 8), "erosion bands")
+
+
+def test_bands_rejects_batches(iwpp):
+    import torch
+
+    dev = torch.device("cuda:0")
+    I, J = synth.c1(H=100, W=90)
+    pairs = [(torch.from_numpy(J).to(dev), torch.from_numpy(I).to(dev))]
+    with pytest.raises(iwpp.IwppError):
+        iwpp.reconstruct_batched(pairs, 8, params={"mode": 2})
 
 
 def test_erosion_batched(iwpp):
