@@ -633,7 +633,9 @@ struct Tile {
   // Bring the tile to a fixed point given its (fixed) halo.  `seeded`: the
   // tile was at a fixed point for an older halo, so only border pixels next
   // to a changed halo pixel can rise at first.
-  __device__ static void solve(L& s, int64_t, int64_t, int sweeps, bool seeded,
+  // Inlined into each caller: the counters and the limit flag then stay in
+  // registers instead of scratch memory.
+  __device__ __forceinline__ static void solve(L& s, int64_t, int64_t, int sweeps, bool seeded,
                                int seed_queue_max, uint32_t waves, uint32_t iter_limit,
                                VisitStats& vs, bool& hit_limit) {
     int budget = sweeps;
@@ -707,7 +709,8 @@ struct Tile {
 };
 
 template <typename T, int CONN, int TH>
-__global__ __launch_bounds__(64) void k_persistent(DevImage one, const DevImage* __restrict__ imgs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_persistent(
+    DevImage one, const DevImage* __restrict__ imgs,
                                                    KParams kp, DevCtl* ctl, int* queue,
                                                    uint32_t* state, uint8_t* visited) {
   persistent_worker<Tile<T, CONN, TH>>(one, imgs, kp, ctl, queue, state, visited);
