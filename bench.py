@@ -432,7 +432,9 @@ def bench_served(args, torch, iwpp):
     pristine = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
     px = [I.size for I, J, _ in pool]
     del pool
-    copies = 8
+    # working markers per pool request: enough that the submitting loop
+    # rarely waits for one to be collected (arrivals stay open-loop)
+    copies = args.copies
     work = [[torch.empty_like(p) for _ in range(copies)] for p in pristine]
     times, idx = synth.c5_arrivals(seed=4, rate=args.rate, duration=args.duration, pool=len(masks))
     srv = iwpp.Server(int(args.budget_gb * 1e9), "u8", 8, streams=args.streams,
@@ -495,7 +497,7 @@ def bench_served(args, torch, iwpp):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "c5", "rate_req_s": args.rate, "duration_s": args.duration,
-                   "pool": len(masks), "streams": args.streams,
+                   "pool": len(masks), "copies": copies, "streams": args.streams,
                    "max_inflight": args.max_inflight, "budget_gb": args.budget_gb, "conn": 8},
         "served": {"requests": len(lat), "errors": errors[0], "req_s": round(len(lat) / wall, 1),
                    "offered_req_s": round(len(times) / args.duration, 1),
@@ -529,8 +531,9 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="c5 seconds of arrivals")
     ap.add_argument("--pool", type=int, default=64, help="c5 distinct requests")
-    ap.add_argument("--streams", type=int, default=4, help="c5 server launch slots")
-    ap.add_argument("--max-inflight", dest="max_inflight", type=int, default=512)
+    ap.add_argument("--copies", type=int, default=32, help="c5 working markers per pool request")
+    ap.add_argument("--streams", type=int, default=2, help="c5 server launch slots")
+    ap.add_argument("--max-inflight", dest="max_inflight", type=int, default=64)
     ap.add_argument("--budget-gb", dest="budget_gb", type=float, default=64.0)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -345,8 +345,8 @@ def autotune(marker, mask, conn: int = 8, stream=None) -> dict:
 class Server:
     """Continuous-batching request server (see iwpp_server_* in iwpp.h)."""
 
-    def __init__(self, budget_bytes: int, dtype: str = "u8", conn: int = 8, streams: int = 4,
-                 max_inflight: int = 8):
+    def __init__(self, budget_bytes: int, dtype: str = "u8", conn: int = 8, streams: int = 2,
+                 max_inflight: int = 64):
         h = ctypes.c_void_p()
         rc = _load().iwpp_server_create(budget_bytes, U8 if dtype == "u8" else I32, conn,
                                         streams, max_inflight, ctypes.byref(h))
