@@ -455,10 +455,10 @@ struct Tile {
   // direction, in any cyclic order) all saw the same tile: it is then at a
   // fixed point for its halo, and this returns true without running the
   // rest of the round and a whole confirming round.
-  __device__ static bool sweep_rounds(L& s, int budget, VisitStats& vs) {
+  __device__ static bool sweep_rounds(L& s, int budget, int first_pass, VisitStats& vs) {
     int quiet = 0, k = 0;
     for (; k < 4 * budget && quiet < 4; ++k) {
-      if (run_pass(s, k & 3))
+      if (run_pass(s, (first_pass + k) & 3))
         quiet = 0;
       else
         ++quiet;
@@ -515,8 +515,13 @@ struct Tile {
   }
 
   // Border pixels a halo value can raise go to queue 0; returns its length.
-  __device__ static int halo_receivers(L& s) {
+  // Border pixels that a neighbour in the halo can raise go to queue 0.
+  // `first_pass` receives the pass that carries such a change inwards first
+  // (0 down for a top row, 1 up for a bottom row, 2 right for a left column,
+  // 3 left for a right column; the first of these that occurs).
+  __device__ static int halo_receivers(L& s, int& first_pass) {
     int n = 0;
+    uint32_t sides = 0;
     for (int base = 0; base < G::RING; base += 64) {
       const int e = base + lane();
       bool r = false;
@@ -534,10 +539,17 @@ struct Tile {
             if (hy >= 0 && hy < TH && hx >= 0 && hx < TW) continue;
             r = r || jv(s, hy, hx) > j;
           }
+          if (r)
+            sides |= (y == 0 ? 1u : 0u) | (y == TH - 1 ? 2u : 0u) | (x == 0 ? 4u : 0u) |
+                     (x == TW - 1 ? 8u : 0u);
         }
       }
       push(s, 0, n, r, idx);
     }
+    uint32_t all = 0;
+    for (int b = 0; b < 4; ++b)
+      if (__ballot((sides >> b) & 1u)) all |= 1u << b;
+    first_pass = all ? __builtin_ctz(all) : 0;
     wsync();
     return n;
   }
@@ -639,8 +651,9 @@ struct Tile {
                                int seed_queue_max, uint32_t waves, uint32_t iter_limit,
                                VisitStats& vs, bool& hit_limit) {
     int budget = sweeps;
+    int first_pass = 0;
     if (seeded) {
-      const int n = halo_receivers(s);
+      const int n = halo_receivers(s, first_pass);
       if (n == 0) return;
       if (n <= seed_queue_max) {
         if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
@@ -648,7 +661,7 @@ struct Tile {
       if (budget < 1) budget = 1;
     }
     for (uint32_t guard = 0;; ++guard) {
-      if (sweep_rounds(s, budget, vs)) return;  // fixed point
+      if (sweep_rounds(s, budget, first_pass, vs)) return;  // fixed point
       const int n = scan_receivers(s);
       if (n == 0) return;
       if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
