@@ -210,10 +210,11 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 // the XCD, which a waiting worker must not do to the tiles others are
 // working on.
 static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                              int grid, uint32_t h, bool& first_pass) {
+                              int grid, uint32_t h, bool& first_pass, bool& ready) {
   const int64_t len = first_pass_len(kp, q);
   int v;
   first_pass = (int64_t)h < len;
+  ready = first_pass;
   if (first_pass) {
     v = (int)first_pass_tile(kp, q, h);
   } else {
@@ -221,7 +222,10 @@ static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp,
     uint32_t nap = 1;
     for (uint32_t w = 0;; ++w) {
       v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= 0) break;
+      if (v >= 0) {
+        ready = w == 0;
+        break;
+      }
       if (v == kSlotStop) return -1;
       if ((w & 63) == 63 && ld_rlx_u32(&ctl->done.v)) return -1;
       if (w > kp.spin_limit) {
@@ -253,13 +257,16 @@ constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
 static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                         int grid, uint32_t pre, bool& first_pass) {
+                         int grid, uint32_t pre, bool& first_pass, uint32_t& ticket,
+                         bool& ready) {
   first_pass = false;
+  ready = false;
   if (pre == kNoTicket) {
     if (ld_rlx_u32(&ctl->done.v)) return -1;
     pre = atomicAdd(&ctl->head[q].v, 1u);
   }
-  return resolve_ticket(ctl, queue, kp, state, q, grid, pre, first_pass);
+  ticket = pre;
+  return resolve_ticket(ctl, queue, kp, state, q, grid, pre, first_pass, ready);
 }
 
 // Gray-level bands: remember that tile t has work of class c for a later
@@ -276,9 +283,17 @@ static __device__ void defer_tile(DevCtl* ctl, const KParams& kp, int t, int c) 
 // While queue q's first pass lasts, the next ticket is taken before the
 // current tile is solved, so its round trip overlaps useful work (a first-
 // pass ticket maps to a tile without waiting).
-static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q) {
-  if (ld_rlx_u32(&ctl->done.v)) return kNoTicket;
-  if ((int64_t)ld_rlx_u32(&ctl->head[q].v) >= first_pass_len(kp, q)) return kNoTicket;
+static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q, int grid,
+                                           uint32_t last, bool backlog) {
+  // Decided without reading anything (a read here would stall the wavefront
+  // before its solve): take the ticket when this worker's last ticket was
+  // far enough inside the queue's first pass that the next one most likely
+  // is too, or when its last ring slot was already filled when it looked (a
+  // backlog: the next slot will not keep the ticket waiting either).  A
+  // ticket taken after the launch ended still returns: the slot wait checks
+  // the done flag.
+  const int64_t per_queue = grid / kp.nq + 1;
+  if (!backlog && (int64_t)last + 2 * per_queue >= first_pass_len(kp, q)) return kNoTicket;
   return atomicAdd(&ctl->head[q].v, 1u);
 }
 
@@ -366,13 +381,16 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
   const int grid = gridDim.x;
   WorkerStats ws;
   uint32_t pre = kNoTicket;  // lane 0: a ticket taken ahead of time
+  uint32_t last = 0;         // lane 0: the last ticket it took
+  bool backlog = false;      // lane 0: its last ring slot was filled when it looked
   for (;;) {
     uint32_t c0 = (uint32_t)now();
     int t = 0, fp = 0;
     if (lead) {
-      bool first_pass = false;
-      t = queue_pop(ctl, queue, kp, state, q, grid, pre, first_pass);
+      bool first_pass = false, ready = false;
+      t = queue_pop(ctl, queue, kp, state, q, grid, pre, first_pass, last, ready);
       fp = first_pass ? 1 : 0;
+      backlog = !first_pass && ready;
       pre = kNoTicket;
     }
     t = __builtin_amdgcn_readfirstlane(t);
@@ -412,7 +430,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
-    if (lead) pre = prefetch_ticket(ctl, kp, q);
+    if (lead) pre = prefetch_ticket(ctl, kp, q, grid, last, backlog);
     TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
               vs, hit);
     uint32_t c3 = (uint32_t)now();
@@ -420,7 +438,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     for (;;) {
       TP::store(s, im, y0, x0, kp.flip);
       int amax = 0;
-      const uint32_t act = TP::activation_mask(s, y0, x0, amax);
+      const uint32_t act = TP::activation_mask(s, y0, x0, kp.band >= 0, amax);
       int cls = 0;
       if (kp.band >= 0) {
         cls = (amax - kp.band_base) >> kp.band_shift;

@@ -331,7 +331,8 @@ struct EdtTile {
       x = TW - 1;
     }
   }
-  __device__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0, int& amax) {
+  __device__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0, bool,
+                                             int& amax) {
     amax = 0;  // no gray-level bands for distances
     uint32_t m = 0;
     for (int base = 0; base < G::RING; base += 64) {

@@ -676,9 +676,11 @@ struct Tile {
   // Neighbour tiles (3x3 grid index) that a changed border pixel can
   // propagate into.  Halo values are the ones seen at load time; they never
   // exceed the current ones, so no needed activation is missed.
-  // `amax` receives the largest value among the border pixels that activate
-  // a neighbour (the class of the visit's fronts for gray-level bands).
-  __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t, int& amax) {
+  // With `want_max`, `amax` receives the largest value among the border
+  // pixels that activate a neighbour (the class of the visit's fronts for
+  // gray-level bands); the wavefront reduction is skipped otherwise.
+  __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t, bool want_max,
+                                             int& amax) {
     uint32_t m = 0;
     int vmax = LO;
     for (int base = 0; base < G::RING; base += 64) {
@@ -711,8 +713,11 @@ struct Tile {
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) vmax = imax(vmax, __shfl_xor(vmax, off));
-    amax = __builtin_amdgcn_readfirstlane(vmax);
+    amax = LO;
+    if (want_max) {
+      for (int off = 32; off > 0; off >>= 1) vmax = imax(vmax, __shfl_xor(vmax, off));
+      amax = __builtin_amdgcn_readfirstlane(vmax);
+    }
     // OR across the wavefront
     uint32_t all = 0;
     for (int d = 0; d < 9; ++d)
@@ -757,7 +762,7 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
             vs, hit);
   TP::store(s, im, y0, x0, kp.flip);
   int amax = 0;
-  const uint32_t act = TP::activation_mask(s, y0, x0, amax);
+  const uint32_t act = TP::activation_mask(s, y0, x0, false, amax);
   if (threadIdx.x == 0) {
     WorkerStats ws;
     ws.add(vs);
