@@ -679,38 +679,43 @@ struct Tile {
   // With `want_max`, `amax` receives the largest value among the border
   // pixels that activate a neighbour (the class of the visit's fronts for
   // gray-level bands); the wavefront reduction is skipped otherwise.
+  // Each side is checked against the halo pixels beyond it (the top and
+  // bottom rows one lane per column, the left and right columns one lane
+  // per row), so every pair of a border pixel and a halo neighbour is seen;
+  // corner pixels are seen from both of their sides.
   __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t, bool want_max,
                                              int& amax) {
     uint32_t m = 0;
     int vmax = LO;
-    for (int base = 0; base < G::RING; base += 64) {
-      const int e = base + lane();
-      if (e >= G::RING) continue;
-      int y, x;
-      ring_pos(e, y, x);
-      const int j = jv(s, y, x);
-      int j0;
-      if (e < TW)
-        j0 = (int)s.b_top[x];
-      else if (e < 2 * TW)
-        j0 = (int)s.b_bot[x];
-      else if (e < 2 * TW + TH - 2)
-        j0 = (int)s.b_left[y];
-      else
-        j0 = (int)s.b_right[y];
-      if (j == j0) continue;
-      for (int d = 0; d < 9; ++d) {
-        const int dy = d / 3 - 1, dx = d % 3 - 1;
-        if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
-        const int hy = y + dy, hx = x + dx;
+    // border pixel (value j) against halo pixel (hy, hx)
+    auto check = [&](int j, int hy, int hx) {
+      const int jh = jv(s, hy, hx);
+      if (j > jh && jh < iv(s, hy, hx)) {
         const int cy = hy < 0 ? 0 : (hy >= TH ? 2 : 1);
         const int cx = hx < 0 ? 0 : (hx >= TW ? 2 : 1);
-        if (cy == 1 && cx == 1) continue;
-        const int jh = jv(s, hy, hx);
-        if (j > jh && jh < iv(s, hy, hx)) {
-          m |= 1u << (cy * 3 + cx);
-          vmax = imax(vmax, j);
-        }
+        m |= 1u << (cy * 3 + cx);
+        vmax = imax(vmax, j);
+      }
+    };
+    {
+      const int x = lane();
+      const int jt = jv(s, 0, x), jb = jv(s, TH - 1, x);
+      const bool ct = jt != (int)s.b_top[x], cb = jb != (int)s.b_bot[x];
+#pragma unroll
+      for (int d = -1; d <= 1; ++d) {
+        if (CONN == 4 && d != 0) continue;
+        if (ct) check(jt, -1, x + d);
+        if (cb) check(jb, TH, x + d);
+      }
+    }
+    for (int y = lane(); y < TH; y += 64) {
+      const int jl = jv(s, y, 0), jr = jv(s, y, TW - 1);
+      const bool cl = jl != (int)s.b_left[y], cr = jr != (int)s.b_right[y];
+#pragma unroll
+      for (int d = -1; d <= 1; ++d) {
+        if (CONN == 4 && d != 0) continue;
+        if (cl) check(jl, y + d, -1);
+        if (cr) check(jr, y + d, TW);
       }
     }
     amax = LO;
