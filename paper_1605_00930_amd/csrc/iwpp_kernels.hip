@@ -478,21 +478,46 @@ struct Tile {
     return m;
   }
 
-  // Every pixel a neighbour can still raise goes to queue 0; returns its length.
+  // Every pixel a neighbour can still raise goes to queue 0; returns its
+  // length.  One lane per column walks down the rows with rows y - 1, y and
+  // y + 1 of J in registers (and, for lanes 0 and 63, the halo column beside
+  // them, as in the passes); the columns beside come from the lanes beside.
+  // A pixel's own value is part of the maximum, which changes nothing: the
+  // test is whether the maximum exceeds it.
   __device__ static int scan_receivers(L& s) {
     int n = 0;
+    const int x = lane();
+    const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
+    int ja = jv(s, -1, x), jb = jv(s, 0, x);
+    int fa = jv(s, -1, fx), fb = jv(s, 0, fx);
     constexpr int R = 8;
 #pragma unroll 1
     for (int yb = 0; yb < TH; yb += R) {
+      int jn[R], fn[R], ii[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        jn[k] = jv(s, yb + k + 1, x);
+        fn[k] = jv(s, yb + k + 1, fx);
+        ii[k] = iv(s, yb + k, x);
+      }
       bool r[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        const int a = G::at(yb + k, lane());
-        const int j = (int)s.J[a], i = (int)s.I[a];
-        r[k] = j < i && nbr_max(s, yb + k, lane()) > j;
+        int m;
+        if (CONN == 8) {
+          const int c = imax(imax(ja, jb), jn[k]);
+          m = max_sides(imax(c, imax(imax(fa, fb), fn[k])), c);
+        } else {
+          m = max_sides(imax(imax(ja, jn[k]), fb), jb);
+        }
+        r[k] = jb < ii[k] && m > jb;
+        ja = jb;
+        jb = jn[k];
+        fa = fb;
+        fb = fn[k];
       }
 #pragma unroll
-      for (int k = 0; k < R; ++k) push(s, 0, n, r[k], (yb + k) * TW + lane());
+      for (int k = 0; k < R; ++k) push(s, 0, n, r[k], (yb + k) * TW + x);
     }
     wsync();
     return n;
