@@ -83,7 +83,6 @@ struct Geo {
   // CU's LDS; an overflowing queue falls back to rounds of passes.
   static constexpr int QCAP = sizeof(T) == 1 ? NPIX / 4 : NPIX / 8;
   static constexpr int NWORDS = NPIX / 32;
-  static constexpr int RING = 2 * TW + 2 * (TH - 2);  // border pixels, each once
   static constexpr int HALO = 2 * (TW + 2) + 2 * TH;  // halo pixels
   __device__ static constexpr int at(int y, int x) { return (y + 1) * P + (x + 1); }
 };
@@ -523,53 +522,49 @@ struct Tile {
     return n;
   }
 
-  __device__ static void ring_pos(int e, int& y, int& x) {
-    if (e < TW) {
-      y = 0;
-      x = e;
-    } else if (e < 2 * TW) {
-      y = TH - 1;
-      x = e - TW;
-    } else if (e < 2 * TW + TH - 2) {
-      y = e - 2 * TW + 1;
-      x = 0;
-    } else {
-      y = e - 2 * TW - (TH - 2) + 1;
-      x = TW - 1;
-    }
-  }
-
-  // Border pixels a halo value can raise go to queue 0; returns its length.
   // Border pixels that a neighbour in the halo can raise go to queue 0.
   // `first_pass` receives the pass that carries such a change inwards first
   // (0 down for a top row, 1 up for a bottom row, 2 right for a left column,
-  // 3 left for a right column; the first of these that occurs).
+  // 3 left for a right column; the first of these that occurs).  The top and
+  // bottom rows go one lane per column, corners included (lanes 0 and 63
+  // also look at the halo column beside them); then the left and right
+  // columns without their corners, one lane per pixel.
   __device__ static int halo_receivers(L& s, int& first_pass) {
     int n = 0;
     uint32_t sides = 0;
-    for (int base = 0; base < G::RING; base += 64) {
-      const int e = base + lane();
-      bool r = false;
-      int idx = 0;
-      if (e < G::RING) {
-        int y, x;
-        ring_pos(e, y, x);
-        idx = y * TW + x;
-        const int j = jv(s, y, x), i = iv(s, y, x);
-        if (j < i) {
-          for (int d = 0; d < 9; ++d) {
-            const int dy = d / 3 - 1, dx = d % 3 - 1;
-            if (d == 4 || (CONN == 4 && dy != 0 && dx != 0)) continue;
-            const int hy = y + dy, hx = x + dx;
-            if (hy >= 0 && hy < TH && hx >= 0 && hx < TW) continue;
-            r = r || jv(s, hy, hx) > j;
-          }
-          if (r)
-            sides |= (y == 0 ? 1u : 0u) | (y == TH - 1 ? 2u : 0u) | (x == 0 ? 4u : 0u) |
-                     (x == TW - 1 ? 8u : 0u);
+    {
+      const int x = lane();
+      const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int y = b == 0 ? 0 : TH - 1, hy = b == 0 ? -1 : TH, iy = b == 0 ? 1 : TH - 2;
+        const int j = jv(s, y, x);
+        int h = jv(s, hy, x);
+        if (CONN == 8) h = imax(h, imax(jv(s, hy, x - 1), jv(s, hy, x + 1)));
+        if (fx != x) {
+          h = imax(h, jv(s, y, fx));
+          if (CONN == 8) h = imax(h, jv(s, iy, fx));
         }
+        const bool r = j < iv(s, y, x) && h > j;
+        if (r) sides |= (1u << b) | (x == 0 ? 4u : 0u) | (x == TW - 1 ? 8u : 0u);
+        push(s, 0, n, r, y * TW + x);
       }
-      push(s, 0, n, r, idx);
+    }
+    constexpr int NS = TH - 2;
+    for (int base = 0; base < 2 * NS; base += 64) {
+      const int e = base + lane();
+      const bool right = e >= NS;
+      const int y = 1 + (right ? e - NS : e);
+      const int x = right ? TW - 1 : 0, hx = right ? TW : -1;
+      bool r = false;
+      if (e < 2 * NS) {
+        const int j = jv(s, y, x);
+        int h = jv(s, y, hx);
+        if (CONN == 8) h = imax(h, imax(jv(s, y - 1, hx), jv(s, y + 1, hx)));
+        r = j < iv(s, y, x) && h > j;
+        if (r) sides |= right ? 8u : 4u;
+      }
+      push(s, 0, n, r, y * TW + x);
     }
     uint32_t all = 0;
     for (int b = 0; b < 4; ++b)
