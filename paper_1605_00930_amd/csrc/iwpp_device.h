@@ -209,8 +209,9 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 // Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
 // the XCD, which a waiting worker must not do to the tiles others are
 // working on.
-static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                              int grid, uint32_t h, bool& first_pass, bool& ready) {
+static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
+                                     const uint8_t* visited, int q, int grid, uint32_t h,
+                                     bool& first_pass, bool& ready, bool& first_visit) {
   const int64_t len = first_pass_len(kp, q);
   int v;
   first_pass = (int64_t)h < len;
@@ -246,9 +247,13 @@ static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp,
   }
   // pending -> running.  A neighbour that asked for this visit finished its
   // marker stores before its request reached the state word, so once the
-  // exchange is complete, the marker reads that follow see them.
+  // exchange is complete, the marker reads that follow see them.  The
+  // visited flag (written by the tile's last owner before it released the
+  // tile) is read in the same round trip.
   __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint8_t seen = ld_coherent(&visited[v]);
   drain_memory();
+  first_visit = seen == 0;
   return v;
 }
 
@@ -256,17 +261,20 @@ constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
-static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int q,
-                         int grid, uint32_t pre, bool& first_pass, uint32_t& ticket,
-                         bool& ready) {
+static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
+                                const uint8_t* visited, int q, int grid, uint32_t pre,
+                                bool& first_pass, uint32_t& ticket, bool& ready,
+                                bool& first_visit) {
   first_pass = false;
   ready = false;
+  first_visit = false;
   if (pre == kNoTicket) {
     if (ld_rlx_u32(&ctl->done.v)) return -1;
     pre = atomicAdd(&ctl->head[q].v, 1u);
   }
   ticket = pre;
-  return resolve_ticket(ctl, queue, kp, state, q, grid, pre, first_pass, ready);
+  return resolve_ticket(ctl, queue, kp, state, visited, q, grid, pre, first_pass, ready,
+                        first_visit);
 }
 
 // Gray-level bands: remember that tile t has work of class c for a later
@@ -385,16 +393,19 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
   bool backlog = false;      // lane 0: its last ring slot was filled when it looked
   for (;;) {
     uint32_t c0 = (uint32_t)now();
-    int t = 0, fp = 0;
+    int t = 0, fp = 0, fv = 0;
     if (lead) {
-      bool first_pass = false, ready = false;
-      t = queue_pop(ctl, queue, kp, state, q, grid, pre, first_pass, last, ready);
+      bool first_pass = false, ready = false, first_visit = false;
+      t = queue_pop(ctl, queue, kp, state, visited, q, grid, pre, first_pass, last, ready,
+                    first_visit);
       fp = first_pass ? 1 : 0;
+      fv = first_visit ? 1 : 0;
       backlog = !first_pass && ready;
       pre = kNoTicket;
     }
     t = __builtin_amdgcn_readfirstlane(t);
     fp = __builtin_amdgcn_readfirstlane(fp);
+    fv = __builtin_amdgcn_readfirstlane(fv);
     uint32_t c1 = (uint32_t)now();
     ws.t_idle += c1 - c0;
     if (t < 0) break;
@@ -424,7 +435,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       }
     }
     ws.visits++;
-    const bool first = ld_coherent(&visited[t]) == 0;
+    const bool first = fv != 0;
     VisitStats vs;
     bool hit = false;
     const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
