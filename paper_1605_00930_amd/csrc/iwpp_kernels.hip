@@ -323,6 +323,23 @@ struct Tile {
     return t;
   }
 
+  // max(t0, prev, and the prev of the lanes on either side), for one
+  // 8-connected step of a pass (t0 holds the pixel's own J and the fill
+  // value).  The DPP reads of prev come two wait states after whatever
+  // wrote it (the first max and the s_nop), so the block needs no other
+  // padding, and the chain through prev is three instructions plus the min
+  // that follows.
+  __device__ static int max8(int prev, int t0) {
+    int b;
+    asm("v_max_i32 %0, %1, %2\n\t"
+        "s_nop 0\n\t"
+        "v_max_i32_dpp %0, %1, %0 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_max_i32_dpp %0, %1, %0 wave_shl:1 row_mask:0xf bank_mask:0xf"
+        : "=&v"(b)
+        : "v"(prev), "v"(t0));
+    return b;
+  }
+
   // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
   // min(I, max(J, the three pixels of the previous row around it)).  The
   // previous row stays in `prev`; its diagonal neighbours come from the lanes
@@ -351,15 +368,14 @@ struct Tile {
       bool changed = false;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        int t = imax(jj[k], prev);
         if (CONN == 8) {
-          t = max_sides(imax(t, fprev), prev);
+          prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
           fprev = ff[k];
+        } else {
+          prev = imin(imax(jj[k], prev), ii[k]);
         }
-        const int v = imin(t, ii[k]);
-        changed = changed || v != jj[k];
-        jj[k] = v;
-        prev = v;
+        changed = changed || prev != jj[k];
+        jj[k] = prev;
       }
 #pragma unroll
       for (int k = 0; k < B; ++k) s.J[G::at(ys + D * (kb + k), x)] = (T)jj[k];
@@ -406,15 +422,14 @@ struct Tile {
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-          int t = imax(jj[k], prev);
           if (CONN == 8) {
-            t = max_sides(imax(t, fprev), prev);
+            prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
             fprev = ff[k];
+          } else {
+            prev = imin(imax(jj[k], prev), ii[k]);
           }
-          const int v = imin(t, ii[k]);
-          dirty = dirty || v != jj[k];
-          jj[k] = v;
-          prev = v;
+          dirty = dirty || prev != jj[k];
+          jj[k] = prev;
         }
         if (live) {
 #pragma unroll
