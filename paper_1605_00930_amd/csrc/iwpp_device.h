@@ -209,7 +209,7 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 // Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
 // the XCD, which a waiting worker must not do to the tiles others are
 // working on.
-static __device__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
+static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
                                      const uint8_t* visited, int q, int grid, uint32_t h,
                                      bool& first_pass, bool& ready, bool& first_visit) {
   const int64_t len = first_pass_len(kp, q);
@@ -261,7 +261,7 @@ constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
-static __device__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
+static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
                                 const uint8_t* visited, int q, int grid, uint32_t pre,
                                 bool& first_pass, uint32_t& ticket, bool& ready,
                                 bool& first_visit) {
@@ -291,7 +291,7 @@ static __device__ void defer_tile(DevCtl* ctl, const KParams& kp, int t, int c) 
 // While queue q's first pass lasts, the next ticket is taken before the
 // current tile is solved, so its round trip overlaps useful work (a first-
 // pass ticket maps to a tile without waiting).
-static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q, int grid,
+static __device__ __forceinline__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q, int grid,
                                            uint32_t last, bool backlog) {
   // Decided without reading anything (a read here would stall the wavefront
   // before its solve): take the ticket when this worker's last ticket was
@@ -313,7 +313,7 @@ static __device__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q
 // after both have landed are the queue slots filled, so a queued tile is
 // always already counted.  Returns 1 if t must be run again (a neighbour
 // asked while it ran), 2 if this visit completed the launch, 0 otherwise.
-static __device__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
+static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
                        const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
                        WorkerStats& ws) {
   const int d = threadIdx.x;

@@ -110,7 +110,7 @@ struct EdtTile {
     }
   }
 
-  __device__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
+  __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
                                      uint32_t) {
     const gptr<const uint32_t> gS = (gptr<const uint32_t>)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
@@ -138,7 +138,7 @@ struct EdtTile {
     wsync();
   }
 
-  __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
+  __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
                                uint32_t) {
     const gptr<uint32_t> gS = (gptr<uint32_t>)im.J;
     const int64_t gx = x0 + lane();
@@ -331,7 +331,7 @@ struct EdtTile {
       x = TW - 1;
     }
   }
-  __device__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0, bool,
+  __device__ __forceinline__ static uint32_t activation_mask(const L& s, int64_t y0, int64_t x0, bool,
                                              int& amax) {
     amax = 0;  // no gray-level bands for distances
     uint32_t m = 0;

@@ -137,7 +137,7 @@ struct Tile {
   // a value.  J is clamped to I on load (a clamped pixel's row is marked
   // dirty so that the clamp reaches memory); returns true if a first visit
   // saw J > I inside the tile.
-  __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
+  __device__ __forceinline__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
                               uint32_t flip) {
     // almost every tile lies inside the image with its halo: its loads need
     // no bounds checks and its two row batches are unrolled
@@ -146,7 +146,7 @@ struct Tile {
                  : load_t<false>(s, im, y0, x0, first, flip);
   }
   template <bool INNER>
-  __device__ static bool load_t(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
+  __device__ __forceinline__ static bool load_t(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
                                 uint32_t flip) {
     // image rows live in global memory: address-space-1 pointers give
     // global_load instructions, which (unlike flat ones) leave the LDS
@@ -214,7 +214,7 @@ struct Tile {
         s.I[yy * G::P + lane()] = (T)b;
       }
     };
-    if (INNER) {
+    if (INNER && G::ROWS <= 2 * B) {
 #pragma unroll
       for (int yb = 0; yb < G::ROWS; yb += B) batch(yb);
     } else {
@@ -255,7 +255,7 @@ struct Tile {
 
   // Re-read the halo of J; the tile's own pixels in LDS are current because
   // this wavefront is their only writer.
-  __device__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
+  __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
                                      uint32_t flip) {
     const T* __restrict__ gJ = (const T*)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
@@ -286,19 +286,31 @@ struct Tile {
     wsync();
   }
 
-  __device__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
+  __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
                                uint32_t flip) {
     const gptr<T> gJ = (gptr<T>)im.J;
     const int64_t gx = x0 + lane();
     const bool col_in = gx < im.W;
     for (int g = 0; g < TH; g += 64) {
       // lane k reports row g + k; the set bits are the rows to write back
-      unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
-      while (rows) {
-        const int y = g + __builtin_ctzll(rows);
-        rows &= rows - 1;
-        const int64_t gy = y0 + y;
-        if (gy < im.H && col_in) st_coherent(&gJ[gy * im.ld + gx], out(s.J[G::at(y, lane())], flip));
+      const unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
+      // eight rows at a time: their LDS reads go out together, then the
+      // stores of the dirty ones
+      constexpr int GR = 8;
+      constexpr int NR = TH < 64 ? TH : 64;
+#pragma unroll 1
+      for (int yb = 0; yb < NR; yb += GR) {
+        const uint32_t bits = (uint32_t)(rows >> yb) & ((1u << GR) - 1);
+        if (!bits) continue;
+        int v[GR];
+#pragma unroll
+        for (int k = 0; k < GR; ++k) v[k] = (int)s.J[G::at(g + yb + k, lane())];
+#pragma unroll
+        for (int k = 0; k < GR; ++k) {
+          const int64_t gy = y0 + g + yb + k;
+          if (((bits >> k) & 1u) && gy < im.H && col_in)
+            st_coherent(&gJ[gy * im.ld + gx], out((T)v[k], flip));
+        }
       }
     }
   }
@@ -718,7 +730,7 @@ struct Tile {
   // bottom rows one lane per column, the left and right columns one lane
   // per row), so every pair of a border pixel and a halo neighbour is seen;
   // corner pixels are seen from both of their sides.
-  __device__ static uint32_t activation_mask(const L& s, int64_t, int64_t, bool want_max,
+  __device__ __forceinline__ static uint32_t activation_mask(const L& s, int64_t, int64_t, bool want_max,
                                              int& amax) {
     uint32_t m = 0;
     int vmax = LO;
