@@ -355,37 +355,33 @@ struct Tile {
   // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
   // min(I, max(J, the three pixels of the previous row around it)).  The
   // previous row stays in `prev`; its diagonal neighbours come from the lanes
-  // beside.  Lanes 0 and 63 also take the halo column beside them (`fprev`,
-  // the previous row's halo pixel); the other lanes read their own column
-  // there, an old value that never exceeds `prev`, so every lane runs the
-  // same instructions.  Changed rows are recorded per batch of B rows.
+  // beside.  Lanes 0 and 63 do not look at the halo columns beside the tile:
+  // the right and left passes take every neighbour there (straight and
+  // diagonal), and a fixed point needs each neighbour relation to be enforced
+  // by one of the four passes, not by all.  Changed rows are recorded per
+  // batch of B rows.
   static constexpr int B = 16;
   template <int D>
   __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
     const int ys = D > 0 ? 0 : TH - 1;
-    const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
     int prev = jv(s, ys - D, x);
-    int fprev = CONN == 8 ? jv(s, ys - D, fx) : LO;
 #pragma unroll 1
     for (int kb = 0; kb < TH; kb += B) {
-      int jj[B], ii[B], ff[B];
+      int jj[B], ii[B];
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int y = ys + D * (kb + k);
         jj[k] = jv(s, y, x);
         ii[k] = iv(s, y, x);
-        if (CONN == 8) ff[k] = jv(s, y, fx);
       }
       bool changed = false;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        if (CONN == 8) {
-          prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
-          fprev = ff[k];
-        } else {
+        if (CONN == 8)
+          prev = imin(max8(prev, jj[k]), ii[k]);
+        else
           prev = imin(imax(jj[k], prev), ii[k]);
-        }
         changed = changed || prev != jj[k];
         jj[k] = prev;
       }
@@ -405,7 +401,9 @@ struct Tile {
 
   // Right (D = +1) or left (D = -1) pass, one lane per row, in groups of 64
   // rows.  Lane 0 also takes the row above the group and lane 63 the row
-  // below it; other lanes read their own row there (harmless, as above).  In
+  // below it (`fprev`); the other lanes read their own row there, an old
+  // value that never exceeds `prev`, so every lane runs the same
+  // instructions.  In
   // 32-row tiles lanes 32..63 follow the halo row below the tile: what they
   // compute is min(I, max of valid lower bounds of R), itself a valid lower
   // bound of R, which is all lane 31 needs from its lower neighbour; they
