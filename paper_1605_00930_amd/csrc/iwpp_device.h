@@ -259,6 +259,28 @@ static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, co
 
 constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 
+// Mid-visit requests.  peek_request() reads the state word of the tile a
+// wavefront is visiting (lane 0; the result is used later, so the read's
+// round trip overlaps work); take_request() with that value returns true if
+// a neighbour asked for the tile since it was taken.  The request is then
+// consumed (pending -> running, as when a tile is taken) and, once the
+// exchange is complete, the neighbour's marker stores are visible, so the
+// caller re-reads its halo and goes on.  A request that lands after the
+// read is seen by the release at the end of the visit as before.
+__device__ __forceinline__ uint32_t peek_request(const uint32_t* word) {
+  uint32_t v = 0;
+  if (threadIdx.x == 0) v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+__device__ __forceinline__ bool take_request(uint32_t* word, uint32_t peeked) {
+  const uint32_t v = __builtin_amdgcn_readfirstlane(peeked);
+  if (!(v & TS_PENDING)) return false;
+  if (threadIdx.x == 0)
+    __hip_atomic_exchange(word, TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  drain_memory();
+  return true;
+}
+
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
 static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
@@ -313,9 +335,11 @@ static __device__ __forceinline__ uint32_t prefetch_ticket(DevCtl* ctl, const KP
 // after both have landed are the queue slots filled, so a queued tile is
 // always already counted.  Returns 1 if t must be run again (a neighbour
 // asked while it ran), 2 if this visit completed the launch, 0 otherwise.
+// With `release` false (a visit that publishes its border and goes on) t
+// stays running and only the requests go out; that returns 0.
 static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
                        const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
-                       WorkerStats& ws) {
+                       WorkerStats& ws, bool release = true) {
   const int d = threadIdx.x;
   int n = -1;
   if (d < 9 && ((act >> d) & 1u)) {
@@ -336,7 +360,7 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
       fresh = __hip_atomic_fetch_or(&state[n], TS_PENDING, __ATOMIC_RELAXED,
                                     __HIP_MEMORY_SCOPE_AGENT) == 0u;
   }
-  if (d == 9) {
+  if (d == 9 && release) {
     uint32_t expect = TS_RUNNING;
     released = __hip_atomic_compare_exchange_strong(
         &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -361,7 +385,7 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
     __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   ws.requeued += nfresh;
-  if (!rel) {
+  if (release && !rel) {
     // running | pending: take the request and run again (the failed release
     // already saw the request, so the halo reads that follow see the
     // neighbour's new border)
@@ -442,11 +466,17 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
     if (lead) pre = prefetch_ticket(ctl, kp, q, grid, last, backlog);
-    TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
-              vs, hit);
-    uint32_t c3 = (uint32_t)now();
-    ws.t_solve += c3 - c2;
+    // one solve and one publication site: a visit may go round this loop
+    // after publishing its border early (streaming tiles) or after a
+    // release that found a neighbour's request (re-run with the new halo)
+    bool seeded = !first, resume = false, early = TP::kStreaming;
+    uint32_t c3 = c2;
     for (;;) {
+      const bool more = TP::solve(s, y0, x0, kp.sweeps, seeded, kp.seed_queue_max,
+                                  kp.queue_waves, kp.spin_limit, vs, hit, &state[t], im, kp.flip,
+                                  resume, early);
+      uint32_t c3a = (uint32_t)now();
+      ws.t_solve += c3a - c3;
       TP::store(s, im, y0, x0, kp.flip);
       int amax = 0;
       const uint32_t act = TP::activation_mask(s, y0, x0, kp.band >= 0, amax);
@@ -456,30 +486,44 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
         if (cls < 0) cls = 0;
       }
       uint32_t c3b = (uint32_t)now();
-      ws.t_store += c3b - c3;
+      ws.t_store += c3b - c3a;
       ws.add(vs);
+      vs = VisitStats();
       if (lead) {
         if (first) st_coherent(&visited[t], (uint8_t)1);
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
+      hit = false;
       // the write-back is complete before anyone is told about it
       drain_memory();
-      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, cls, ws);
+      // with `more` the border raised a neighbour before the tile's fixed
+      // point: the requests go out now and the rounds go on
+      const bool release = !(TP::kStreaming && more);
+      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, cls, ws, release);
       if (res == 2) stop_all(ctl, queue, kp, grid);
       uint32_t c4 = (uint32_t)now();
       ws.t_sync += c4 - c3b;
+      c3 = c4;
+      if constexpr (TP::kStreaming) {
+        if (!release) {
+          TP::clear_dirty(s);
+          TP::snapshot_border(s);
+          wsync();
+          seeded = false;
+          resume = true;
+          early = false;
+          continue;
+        }
+      }
       if (res != 1) break;
       // a neighbour changed while this tile ran: reload the halo, continue
-      vs = VisitStats();
-      hit = false;
       TP::reload_halo(s, im, y0, x0, kp.flip);
-      uint32_t c5 = (uint32_t)now();
-      ws.t_load += c5 - c4;
-      TP::solve(s, y0, x0, kp.sweeps, true, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
-                vs, hit);
       c3 = (uint32_t)now();
-      ws.t_solve += c3 - c5;
+      ws.t_load += c3 - c4;
+      seeded = true;
+      resume = false;
+      early = TP::kStreaming;
     }
   }
   if (lead) ws.flush(ctl);

@@ -296,8 +296,10 @@ struct EdtTile {
   // Rounds until one changes nothing: the tile is then at a fixed point of
   // the propagation for its halo (the reconstruction tile's scan-round and
   // queue parameters do not apply).
-  __device__ static void solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
-                               uint32_t iter_limit, VisitStats& vs, bool& hit_limit) {
+  static constexpr bool kStreaming = false;
+  __device__ static bool solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
+                               uint32_t iter_limit, VisitStats& vs, bool& hit_limit, uint32_t*,
+                               const DevImage&, uint32_t, bool, bool) {
     // passes down, up, right, left, round after round, until four in a row
     // change nothing: those four saw the same tile in every direction
     int quiet = 0;
@@ -309,9 +311,10 @@ struct EdtTile {
       if ((k & 3u) == 3u) vs.rounds++;
       if (k >= 4u * iter_limit) {
         hit_limit = true;
-        return;
+        return false;
       }
     }
+    return false;
   }
 
   // Neighbour tiles (3x3 grid index) with a halo pixel to which a changed

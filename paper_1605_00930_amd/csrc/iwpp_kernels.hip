@@ -253,12 +253,21 @@ struct Tile {
     }
   }
 
-  // Re-read the halo of J; the tile's own pixels in LDS are current because
-  // this wavefront is their only writer.
+  // Re-read the halo of J for a re-run after a release that found a
+  // request; the tile's own pixels in LDS are current because this
+  // wavefront is their only writer.
   __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
                                      uint32_t flip) {
-    const T* __restrict__ gJ = (const T*)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    refresh_halo(s, im, y0, x0, flip);
+    snapshot_border(s);
+    wsync();
+  }
+
+  // Re-read the halo of J (and nothing else).
+  __device__ __forceinline__ static void refresh_halo(L& s, const DevImage& im, int64_t y0,
+                                                      int64_t x0, uint32_t flip) {
+    const T* __restrict__ gJ = (const T*)im.J;
     for (int e = lane(); e < G::HALO; e += 64) {
       int y, x;
       if (e < TW + 2) {
@@ -281,8 +290,6 @@ struct Tile {
         s.J[G::at(y, x)] = (T)imin(j, i);
       }
     }
-    wsync();
-    snapshot_border(s);
     wsync();
   }
 
@@ -479,16 +486,41 @@ struct Tile {
   // direction, in any cyclic order) all saw the same tile: it is then at a
   // fixed point for its halo, and this returns true without running the
   // rest of the round and a whole confirming round.
-  __device__ static bool sweep_rounds(L& s, int budget, int first_pass, VisitStats& vs) {
+  // uint8 tiles, whose rounds are long, also keep the seams moving while
+  // they work (both make a visit's chain of tile hops shorter):
+  // - after a round that left work, `early`: if the tile's border now
+  //   raises a neighbour, stop here (kEarly) so that the caller publishes
+  //   the border and resumes;
+  // - after a round that left work, a neighbour's request on the tile's
+  //   state word (`watch`; null for none) is taken now: the halo is re-read
+  //   and the rounds go on, instead of a re-run after this visit.
+  static constexpr bool kStreaming = sizeof(T) == 1;
+  enum { kRoundsLeft = 0, kFixed = 1, kEarly = 2 };
+  __device__ static int sweep_rounds(L& s, int budget, int first_pass, VisitStats& vs,
+                                     uint32_t* watch, const DevImage& im, int64_t y0, int64_t x0,
+                                     uint32_t flip, bool early) {
     int quiet = 0, k = 0;
+    int res = kRoundsLeft;
     for (; k < 4 * budget && quiet < 4; ++k) {
       if (run_pass(s, (first_pass + k) & 3))
         quiet = 0;
       else
         ++quiet;
+      if (kStreaming && watch && (k & 3) == 3 && quiet < 4) {
+        int amax;
+        if (early && activation_mask(s, y0, x0, false, amax) != 0u) {
+          res = kEarly;
+          ++k;
+          break;
+        }
+        if (take_request(watch, peek_request(watch))) {
+          refresh_halo(s, im, y0, x0, flip);
+          quiet = 0;
+        }
+      }
     }
     vs.rounds += (uint32_t)((k + 3) / 4);
-    return quiet >= 4;
+    return quiet >= 4 ? kFixed : res;
   }
 
   // ---------------------------------------------------------- seeds
@@ -687,35 +719,47 @@ struct Tile {
   }
 
   // ---------------------------------------------------------- visit
-  // Bring the tile to a fixed point given its (fixed) halo.  `seeded`: the
-  // tile was at a fixed point for an older halo, so only border pixels next
-  // to a changed halo pixel can rise at first.
+  // Bring the tile to a fixed point given its halo.  `seeded`: the tile was
+  // at a fixed point for an older halo, so only border pixels next to a
+  // changed halo pixel can rise at first.  `resume`: go on with rounds
+  // after an early return.  `early`: the solve may return true before the
+  // fixed point, once its border raises a neighbour (sweep_rounds).
   // Inlined into each caller: the counters and the limit flag then stay in
   // registers instead of scratch memory.
-  __device__ __forceinline__ static void solve(L& s, int64_t, int64_t, int sweeps, bool seeded,
+  __device__ __forceinline__ static bool solve(L& s, int64_t y0, int64_t x0, int sweeps, bool seeded,
                                int seed_queue_max, uint32_t waves, uint32_t iter_limit,
-                               VisitStats& vs, bool& hit_limit) {
+                               VisitStats& vs, bool& hit_limit, uint32_t* watch,
+                               const DevImage& im, uint32_t flip, bool resume, bool early) {
     int budget = sweeps;
     int first_pass = 0;
-    if (seeded) {
+    if (resume) {
+      if (budget < 1) budget = 1;
+    } else if (seeded) {
       const int n = halo_receivers(s, first_pass);
-      if (n == 0) return;
+      if (n == 0) return false;
       if (n <= seed_queue_max) {
-        if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
+        if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return false;
       }
       if (budget < 1) budget = 1;
     }
     for (uint32_t guard = 0;; ++guard) {
-      if (sweep_rounds(s, budget, first_pass, vs)) return;  // fixed point
+      const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, flip, early);
+      if (r == kFixed) return false;
+      if (r == kEarly) return true;
       const int n = scan_receivers(s);
-      if (n == 0) return;
-      if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return;
+      if (n == 0) return false;
+      if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return false;
       if (budget < 1) budget = 1;
       if (guard >= iter_limit) {
         hit_limit = true;
-        return;
+        return false;
       }
     }
+  }
+
+  __device__ static void clear_dirty(L& s) {
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    wsync();
   }
 
   // Neighbour tiles (3x3 grid index) that a changed border pixel can
@@ -809,7 +853,7 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   bool hit = false;
   const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
   TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
-            vs, hit);
+            vs, hit, nullptr, im, kp.flip, false, false);
   TP::store(s, im, y0, x0, kp.flip);
   int amax = 0;
   const uint32_t act = TP::activation_mask(s, y0, x0, false, amax);
