@@ -362,39 +362,49 @@ struct Tile {
   // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
   // min(I, max(J, the three pixels of the previous row around it)).  The
   // previous row stays in `prev`; its diagonal neighbours come from the lanes
-  // beside.  Lanes 0 and 63 do not look at the halo columns beside the tile:
-  // the right and left passes take every neighbour there (straight and
-  // diagonal), and a fixed point needs each neighbour relation to be enforced
-  // by one of the four passes, not by all.  Changed rows are recorded per
-  // batch of B rows.
+  // beside.  A fixed point needs every neighbour relation to be enforced by
+  // one of the four passes, not by all, so the passes share the halo: the
+  // vertical passes take the halo rows above and below the tile, the
+  // horizontal passes the halo columns beside it.  The four halo corners are
+  // reached by neither lane scheme; lanes 0 and 63 take the two corners
+  // beside the pass's first previous row at its first step.
+  // Changes are collected as bits (`acc`, one bitop per step) and reported
+  // per batch of B rows.
+  // Rows go in batches of B; the LDS reads of the next batch are issued
+  // before the current batch is worked, so their latency overlaps it (the
+  // next batch's rows are not written by the current one).
   static constexpr int B = 16;
+  static_assert(TH % (2 * B) == 0, "the vertical pass works two batches per iteration");
   template <int D>
   __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
     const int ys = D > 0 ? 0 : TH - 1;
+    const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
     int prev = jv(s, ys - D, x);
-#pragma unroll 1
-    for (int kb = 0; kb < TH; kb += B) {
-      int jj[B], ii[B];
+    int corner = CONN == 8 ? jv(s, ys - D, fx) : LO;  // other lanes: their own column
+    auto fetch = [&](int kb, int (&jj)[B], int (&ii)[B]) {
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int y = ys + D * (kb + k);
         jj[k] = jv(s, y, x);
         ii[k] = iv(s, y, x);
       }
-      bool changed = false;
+    };
+    auto work = [&](int kb, int (&jj)[B], const int (&ii)[B]) {
+      uint32_t acc = 0;
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         if (CONN == 8)
-          prev = imin(max8(prev, jj[k]), ii[k]);
+          prev = imin(max8(prev, k == 0 ? imax(jj[0], corner) : jj[k]), ii[k]);
         else
           prev = imin(imax(jj[k], prev), ii[k]);
-        changed = changed || prev != jj[k];
+        acc |= (uint32_t)(prev ^ jj[k]);
         jj[k] = prev;
       }
+      corner = LO;
 #pragma unroll
       for (int k = 0; k < B; ++k) s.J[G::at(ys + D * (kb + k), x)] = (T)jj[k];
-      if (__ballot(changed)) {
+      if (__ballot(acc != 0u)) {
         // rows kb .. kb + B - 1 of the pass, i.e. this block of tile rows
         const int y0 = D > 0 ? kb : TH - kb - B;
         const uint64_t blk = ((1ull << B) - 1) << (y0 & 63);
@@ -403,18 +413,30 @@ struct Tile {
         else
           d1 |= blk;
       }
+    };
+    int ja[B], ia[B], jb[B], ib[B];
+    fetch(0, ja, ia);
+#pragma unroll 1
+    for (int kb = 0; kb < TH; kb += 2 * B) {
+      fetch(kb + B, jb, ib);
+      work(kb, ja, ia);
+      if (kb + 2 * B < TH) fetch(kb + 2 * B, ja, ia);
+      work(kb + B, jb, ib);
     }
   }
 
   // Right (D = +1) or left (D = -1) pass, one lane per row, in groups of 64
-  // rows.  Lane 0 also takes the row above the group and lane 63 the row
-  // below it (`fprev`); the other lanes read their own row there, an old
-  // value that never exceeds `prev`, so every lane runs the same
-  // instructions.  In
-  // 32-row tiles lanes 32..63 follow the halo row below the tile: what they
-  // compute is min(I, max of valid lower bounds of R), itself a valid lower
-  // bound of R, which is all lane 31 needs from its lower neighbour; they
-  // write nothing.
+  // rows: each pixel takes min(I, max(J, the three pixels of the previous
+  // column around it)).  The halo rows above and below the tile are left to
+  // the vertical passes (see above).  In tiles of more than 64 rows, lane 0
+  // also takes the row above its group and lane 63 the row below it
+  // (`fprev`; other lanes read their own row there, an old value that never
+  // exceeds `prev`): the diagonal relations between a halo column and the
+  // first or last row of a group are reached by no other pass.  In 32-row
+  // tiles lanes 32..63 follow the halo row below the tile: what they compute
+  // is min(I, max of valid lower bounds of R), itself a valid lower bound of
+  // R, which is all lane 31 needs from its lower neighbour; they write
+  // nothing.
   template <int D>
   __device__ static void pass_horz(L& s, uint64_t& d0, uint64_t& d1) {
 #pragma unroll 1
@@ -423,10 +445,11 @@ struct Tile {
       const bool live = lane() < nrows;
       const int yc = live ? g + lane() : TH;
       const int xs = D > 0 ? 0 : TW - 1;
+      constexpr bool kFill = CONN == 8 && TH > 64;
       const int fy = lane() == 0 ? g - 1 : (lane() == 63 && live ? g + 64 : yc);
       int prev = jv(s, yc, xs - D);
-      int fprev = CONN == 8 ? jv(s, fy, xs - D) : LO;
-      bool dirty = false;
+      int fprev = kFill ? jv(s, fy, xs - D) : LO;
+      uint32_t acc = 0;
 #pragma unroll 1
       for (int kb = 0; kb < TW; kb += B) {
         int jj[B], ii[B], ff[B];
@@ -435,17 +458,19 @@ struct Tile {
           const int x = xs + D * (kb + k);
           jj[k] = jv(s, yc, x);
           ii[k] = iv(s, yc, x);
-          if (CONN == 8) ff[k] = jv(s, fy, x);
+          if (kFill) ff[k] = jv(s, fy, x);
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-          if (CONN == 8) {
+          if (kFill) {
             prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
             fprev = ff[k];
+          } else if (CONN == 8) {
+            prev = imin(max8(prev, jj[k]), ii[k]);
           } else {
             prev = imin(imax(jj[k], prev), ii[k]);
           }
-          dirty = dirty || prev != jj[k];
+          acc |= (uint32_t)(prev ^ jj[k]);
           jj[k] = prev;
         }
         if (live) {
@@ -453,7 +478,7 @@ struct Tile {
           for (int k = 0; k < B; ++k) s.J[G::at(yc, xs + D * (kb + k))] = (T)jj[k];
         }
       }
-      const uint64_t b = __ballot(live && dirty);
+      const uint64_t b = __ballot(live && acc != 0u);
       if (g == 0)
         d0 |= b;
       else

@@ -303,6 +303,32 @@ def random_pair_above(rng: np.random.Generator, H: int, W: int, dtype,
     return I.astype(dtype), J.astype(dtype)
 
 
+def diagonal_corridor(H: int, W: int, dtype, direction: int, offset: int,
+                      value: int | None = None):
+    """A 1-pixel-wide diagonal corridor on a zero background, seeded at one end.
+
+    direction +1: pixels (y, y + offset); direction -1: pixels (y, offset - y).
+    The mask holds ``value`` (200 for uint8, 10**6 for int32) on the corridor;
+    the marker is zero except at the corridor's first pixel (smallest y), which
+    holds ``value``.  Two corridor pixels touch only diagonally, so a front
+    along it crosses every tile boundary it meets through a corner or a
+    diagonal neighbour.
+    """
+    dtype = np.dtype(dtype)
+    if value is None:
+        value = 200 if dtype == np.uint8 else 10 ** 6
+    I = np.zeros((H, W), dtype)
+    J = np.zeros((H, W), dtype)
+    ys = np.arange(H)
+    xs = ys + offset if direction > 0 else offset - ys
+    ok = (xs >= 0) & (xs < W)
+    ys, xs = ys[ok], xs[ok]
+    if len(ys):
+        I[ys, xs] = value
+        J[ys[0], xs[0]] = value
+    return I, J
+
+
 def sha256(*arrays: np.ndarray) -> str:
     h = hashlib.sha256()
     for a in arrays:

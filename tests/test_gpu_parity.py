@@ -340,3 +340,25 @@ def test_c2_full_size_bit_exact(iwpp):
     announce("c2 full 4096x4096 u8 conn 8")
     got, st = run(iwpp, I, J, 8)
     same(got, expect(I, J, 8), "c2 full")
+
+
+# ------------------------------------------------------------------ diagonal seams
+
+
+@pytest.mark.parametrize("dtype,tile_h", [(np.uint8, None), (np.uint8, 128), (np.int32, None),
+                                          (np.int32, 64)])
+def test_diagonal_corridors_cross_tile_corners(iwpp, dtype, tile_h):
+    """A front that can only step diagonally from tile to tile: through tile
+    corners (offset 0 on a square grid of tiles), next to them, and across
+    the row groups of 128-row tiles.  Each corridor is one case."""
+    H, W = 300, 330
+    params = {} if tile_h is None else {"tile_h": tile_h}
+    for direction, offset in [(1, 0), (1, 1), (1, -1), (1, 64), (1, -64), (1, 63),
+                              (-1, 127), (-1, 128), (-1, 191), (-1, 255), (-1, 256)]:
+        I, J = synth.diagonal_corridor(H, W, dtype, direction, offset)
+        announce("diagonal %s tile_h %s dir %d offset %d" % (np.dtype(dtype), tile_h,
+                                                             direction, offset))
+        want = expect(I, J, 8)
+        assert int(want.astype(np.int64).sum()) > int(J.astype(np.int64).sum())
+        got, _ = run(iwpp, I, J, 8, params=params)
+        same(got, want, "diagonal dir %d offset %d" % (direction, offset))
