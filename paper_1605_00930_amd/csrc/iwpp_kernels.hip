@@ -359,6 +359,24 @@ struct Tile {
     return b;
   }
 
+  // One 8-connected uint8 step: p <- min(ii, max(t0, p and the p of the
+  // lanes on either side)), and acc += (p as it came in) ^ jprev, the change
+  // made by the step before (jprev is that step's old value; uint8 values
+  // keep the sum of a batch's changes far below 2^32, so it is zero exactly
+  // when nothing changed).  The add sits between the write of p and its DPP
+  // reads, which then come two wait states after it with no padding.
+  __device__ static int step8_u8(int p, uint32_t& acc, int t0, int jprev, int ii) {
+    int b, r;
+    asm("v_max_i32 %1, %3, %4\n\t"
+        "v_xad_u32 %2, %3, %5, %2\n\t"
+        "v_max_i32_dpp %1, %3, %1 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_max_i32_dpp %1, %3, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_min_i32 %0, %1, %6"
+        : "=v"(r), "=&v"(b), "+v"(acc)
+        : "v"(p), "v"(t0), "v"(jprev), "v"(ii));
+    return r;
+  }
+
   // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
   // min(I, max(J, the three pixels of the previous row around it)).  The
   // previous row stays in `prev`; its diagonal neighbours come from the lanes
@@ -392,14 +410,26 @@ struct Tile {
     };
     auto work = [&](int kb, int (&jj)[B], const int (&ii)[B]) {
       uint32_t acc = 0;
+      if constexpr (CONN == 8 && sizeof(T) == 1) {
+        int jprev = prev;  // the first step sees no change before it
 #pragma unroll
-      for (int k = 0; k < B; ++k) {
-        if (CONN == 8)
-          prev = imin(max8(prev, k == 0 ? imax(jj[0], corner) : jj[k]), ii[k]);
-        else
-          prev = imin(imax(jj[k], prev), ii[k]);
-        acc |= (uint32_t)(prev ^ jj[k]);
-        jj[k] = prev;
+        for (int k = 0; k < B; ++k) {
+          const int old = jj[k];
+          prev = step8_u8(prev, acc, k == 0 ? imax(old, corner) : old, jprev, ii[k]);
+          jprev = old;
+          jj[k] = prev;
+        }
+        acc += (uint32_t)(prev ^ jprev);
+      } else {
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          if (CONN == 8)
+            prev = imin(max8(prev, k == 0 ? imax(jj[0], corner) : jj[k]), ii[k]);
+          else
+            prev = imin(imax(jj[k], prev), ii[k]);
+          acc |= (uint32_t)(prev ^ jj[k]);
+          jj[k] = prev;
+        }
       }
       corner = LO;
 #pragma unroll
@@ -416,7 +446,9 @@ struct Tile {
     };
     int ja[B], ia[B], jb[B], ib[B];
     fetch(0, ja, ia);
-#pragma unroll 1
+    // up to 64 rows the loop is unrolled: no value is carried round it, so
+    // the compiler keeps knowing that uint8 values need no masking
+#pragma unroll(TH <= 64 ? TH / (2 * B) : 1)
     for (int kb = 0; kb < TH; kb += 2 * B) {
       fetch(kb + B, jb, ib);
       work(kb, ja, ia);
