@@ -457,6 +457,78 @@ struct Tile {
     }
   }
 
+  // A 16-column block of a uint8, 8-connected horizontal pass, in one asm
+  // block: columns c0 .. c0 + 15 of one row, held packed four to a dword
+  // (byte e of the block is byte e % 4 of dword e / 4), worked in
+  // increasing (D = +1) or decreasing (D = -1) column order.  Each step is
+  // five instructions: b = max(p, J), the packing of the step before's
+  // result into `ow`, two DPP maxima with the lanes beside, p = min(b, I).
+  // The packing sits between the write of p and its DPP reads, which then
+  // come two wait states after it; the first step has an s_nop there
+  // instead, and an s_nop after the last packing keeps the next reader of
+  // `ow` a wait state away from that partial write.
+#define IWPP_HS(JW, S) "v_max_i32_sdwa %1, %0, %" #JW " dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_" #S "\n\t"
+#define IWPP_HP(OW, S) "v_mov_b32_sdwa %" #OW ", %0 dst_sel:BYTE_" #S " dst_unused:UNUSED_PRESERVE src0_sel:DWORD\n\t"
+#define IWPP_HT(IW, S)                                                 \
+  "v_max_i32_dpp %1, %0, %1 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t" \
+  "v_max_i32_dpp %1, %0, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t" \
+  "v_min_i32_sdwa %0, %1, %" #IW " dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_" #S "\n\t"
+#define IWPP_NOP "s_nop 0\n\t"
+  template <int D>
+  __device__ static void hblock_u8(int& p, const uint32_t (&jw)[4], const uint32_t (&iw)[4],
+                                   uint32_t (&ow)[4]) {
+    int b;
+    if constexpr (D > 0) {
+      asm(
+          IWPP_HS(6, 0) IWPP_NOP IWPP_HT(10, 0)
+          IWPP_HS(6, 1) IWPP_HP(2, 0) IWPP_HT(10, 1)
+          IWPP_HS(6, 2) IWPP_HP(2, 1) IWPP_HT(10, 2)
+          IWPP_HS(6, 3) IWPP_HP(2, 2) IWPP_HT(10, 3)
+          IWPP_HS(7, 0) IWPP_HP(2, 3) IWPP_HT(11, 0)
+          IWPP_HS(7, 1) IWPP_HP(3, 0) IWPP_HT(11, 1)
+          IWPP_HS(7, 2) IWPP_HP(3, 1) IWPP_HT(11, 2)
+          IWPP_HS(7, 3) IWPP_HP(3, 2) IWPP_HT(11, 3)
+          IWPP_HS(8, 0) IWPP_HP(3, 3) IWPP_HT(12, 0)
+          IWPP_HS(8, 1) IWPP_HP(4, 0) IWPP_HT(12, 1)
+          IWPP_HS(8, 2) IWPP_HP(4, 1) IWPP_HT(12, 2)
+          IWPP_HS(8, 3) IWPP_HP(4, 2) IWPP_HT(12, 3)
+          IWPP_HS(9, 0) IWPP_HP(4, 3) IWPP_HT(13, 0)
+          IWPP_HS(9, 1) IWPP_HP(5, 0) IWPP_HT(13, 1)
+          IWPP_HS(9, 2) IWPP_HP(5, 1) IWPP_HT(13, 2)
+          IWPP_HS(9, 3) IWPP_HP(5, 2) IWPP_HT(13, 3)
+          IWPP_HP(5, 3) IWPP_NOP
+          : "+v"(p), "=&v"(b), "+v"(ow[0]), "+v"(ow[1]), "+v"(ow[2]), "+v"(ow[3])
+          : "v"(jw[0]), "v"(jw[1]), "v"(jw[2]), "v"(jw[3]), "v"(iw[0]), "v"(iw[1]), "v"(iw[2]),
+            "v"(iw[3]));
+    } else {
+      asm(
+          IWPP_HS(9, 3) IWPP_NOP IWPP_HT(13, 3)
+          IWPP_HS(9, 2) IWPP_HP(5, 3) IWPP_HT(13, 2)
+          IWPP_HS(9, 1) IWPP_HP(5, 2) IWPP_HT(13, 1)
+          IWPP_HS(9, 0) IWPP_HP(5, 1) IWPP_HT(13, 0)
+          IWPP_HS(8, 3) IWPP_HP(5, 0) IWPP_HT(12, 3)
+          IWPP_HS(8, 2) IWPP_HP(4, 3) IWPP_HT(12, 2)
+          IWPP_HS(8, 1) IWPP_HP(4, 2) IWPP_HT(12, 1)
+          IWPP_HS(8, 0) IWPP_HP(4, 1) IWPP_HT(12, 0)
+          IWPP_HS(7, 3) IWPP_HP(4, 0) IWPP_HT(11, 3)
+          IWPP_HS(7, 2) IWPP_HP(3, 3) IWPP_HT(11, 2)
+          IWPP_HS(7, 1) IWPP_HP(3, 2) IWPP_HT(11, 1)
+          IWPP_HS(7, 0) IWPP_HP(3, 1) IWPP_HT(11, 0)
+          IWPP_HS(6, 3) IWPP_HP(3, 0) IWPP_HT(10, 3)
+          IWPP_HS(6, 2) IWPP_HP(2, 3) IWPP_HT(10, 2)
+          IWPP_HS(6, 1) IWPP_HP(2, 2) IWPP_HT(10, 1)
+          IWPP_HS(6, 0) IWPP_HP(2, 1) IWPP_HT(10, 0)
+          IWPP_HP(2, 0) IWPP_NOP
+          : "+v"(p), "=&v"(b), "+v"(ow[0]), "+v"(ow[1]), "+v"(ow[2]), "+v"(ow[3])
+          : "v"(jw[0]), "v"(jw[1]), "v"(jw[2]), "v"(jw[3]), "v"(iw[0]), "v"(iw[1]), "v"(iw[2]),
+            "v"(iw[3]));
+    }
+  }
+#undef IWPP_HS
+#undef IWPP_HP
+#undef IWPP_HT
+#undef IWPP_NOP
+
   // Right (D = +1) or left (D = -1) pass, one lane per row, in groups of 64
   // rows: each pixel takes min(I, max(J, the three pixels of the previous
   // column around it)).  The halo rows above and below the tile are left to
@@ -482,6 +554,19 @@ struct Tile {
       int prev = jv(s, yc, xs - D);
       int fprev = kFill ? jv(s, fy, xs - D) : LO;
       uint32_t acc = 0;
+      if constexpr (CONN == 8 && sizeof(T) == 1 && !kFill && B == 16) {
+        // packed blocks of 16 columns, one b128 read of J and of I each
+#pragma unroll 1
+        for (int kb = 0; kb < TW; kb += B) {
+          const int c0 = D > 0 ? kb : TW - B - kb;
+          uint32_t jw[4], iw[4], ow[4] = {0u, 0u, 0u, 0u};
+          __builtin_memcpy(jw, &s.J[G::at(yc, c0)], 16);
+          __builtin_memcpy(iw, &s.I[G::at(yc, c0)], 16);
+          hblock_u8<D>(prev, jw, iw, ow);
+          acc |= (ow[0] ^ jw[0]) | (ow[1] ^ jw[1]) | (ow[2] ^ jw[2]) | (ow[3] ^ jw[3]);
+          if (live) __builtin_memcpy(&s.J[G::at(yc, c0)], ow, 16);
+        }
+      } else {
 #pragma unroll 1
       for (int kb = 0; kb < TW; kb += B) {
         int jj[B], ii[B], ff[B];
@@ -509,6 +594,7 @@ struct Tile {
 #pragma unroll
           for (int k = 0; k < B; ++k) s.J[G::at(yc, xs + D * (kb + k))] = (T)jj[k];
         }
+      }
       }
       const uint64_t b = __ballot(live && acc != 0u);
       if (g == 0)
