@@ -359,16 +359,15 @@ struct Tile {
     return b;
   }
 
-  // One 8-connected uint8 step: p <- min(ii, max(t0, p and the p of the
-  // lanes on either side)), and acc += (p as it came in) ^ jprev, the change
-  // made by the step before (jprev is that step's old value; uint8 values
-  // keep the sum of a batch's changes far below 2^32, so it is zero exactly
-  // when nothing changed).  The add sits between the write of p and its DPP
+  // One 8-connected step: returns min(ii, max(t0, p and the p of the lanes
+  // on either side)), and sets acc |= (p as it came in) ^ jprev, the change
+  // made by the step before (jprev is that step's old value; bitop3 0xbe is
+  // s2 | (s0 ^ s1)).  That bitop sits between the write of p and its DPP
   // reads, which then come two wait states after it with no padding.
-  __device__ static int step8_u8(int p, uint32_t& acc, int t0, int jprev, int ii) {
+  __device__ static int step8(int p, uint32_t& acc, int t0, int jprev, int ii) {
     int b, r;
     asm("v_max_i32 %1, %3, %4\n\t"
-        "v_xad_u32 %2, %3, %5, %2\n\t"
+        "v_bitop3_b32 %2, %3, %5, %2 bitop3:0xbe\n\t"
         "v_max_i32_dpp %1, %3, %1 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
         "v_max_i32_dpp %1, %3, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
         "v_min_i32 %0, %1, %6"
@@ -410,16 +409,16 @@ struct Tile {
     };
     auto work = [&](int kb, int (&jj)[B], const int (&ii)[B]) {
       uint32_t acc = 0;
-      if constexpr (CONN == 8 && sizeof(T) == 1) {
+      if constexpr (CONN == 8) {
         int jprev = prev;  // the first step sees no change before it
 #pragma unroll
         for (int k = 0; k < B; ++k) {
           const int old = jj[k];
-          prev = step8_u8(prev, acc, k == 0 ? imax(old, corner) : old, jprev, ii[k]);
+          prev = step8(prev, acc, k == 0 ? imax(old, corner) : old, jprev, ii[k]);
           jprev = old;
           jj[k] = prev;
         }
-        acc += (uint32_t)(prev ^ jprev);
+        acc |= (uint32_t)(prev ^ jprev);
       } else {
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -577,18 +576,28 @@ struct Tile {
           ii[k] = iv(s, yc, x);
           if (kFill) ff[k] = jv(s, fy, x);
         }
+        if constexpr (CONN == 8 && !kFill) {
+          int jprev = prev;  // the first step sees no change before it
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          if (kFill) {
-            prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
-            fprev = ff[k];
-          } else if (CONN == 8) {
-            prev = imin(max8(prev, jj[k]), ii[k]);
-          } else {
-            prev = imin(imax(jj[k], prev), ii[k]);
+          for (int k = 0; k < B; ++k) {
+            const int old = jj[k];
+            prev = step8(prev, acc, old, jprev, ii[k]);
+            jprev = old;
+            jj[k] = prev;
           }
-          acc |= (uint32_t)(prev ^ jj[k]);
-          jj[k] = prev;
+          acc |= (uint32_t)(prev ^ jprev);
+        } else {
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            if (kFill) {
+              prev = imin(max8(prev, imax(jj[k], fprev)), ii[k]);
+              fprev = ff[k];
+            } else {
+              prev = imin(imax(jj[k], prev), ii[k]);
+            }
+            acc |= (uint32_t)(prev ^ jj[k]);
+            jj[k] = prev;
+          }
         }
         if (live) {
 #pragma unroll
