@@ -485,6 +485,10 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
     rc = b.ensure(ntiles, kp.qcap * (uint32_t)kp.nq, nimg, false);
     if (rc) return rc;
     order_for(rp.order_seed, ntiles, &kp.order_mul, &kp.order_add);
+    if (rp.order_seed == 0 && nimg == 1 && !d_imgs) {
+      kp.phase_tx = one.tiles_x;
+      kp.phase_ty = one.tiles_y;
+    }
     HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, st));
     b.timed = false;
     if (rp.timing) {

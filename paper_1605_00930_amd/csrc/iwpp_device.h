@@ -152,10 +152,28 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
   return len;
 }
 
+// Four-phase first pass of one image: position i of the pass goes to the
+// tiles whose row and column are both even first, then (even row, odd
+// column), (odd row, even column) and (odd, odd), each group in raster
+// order.  No two tiles of a group touch, so tiles that run at the same time
+// are seldom neighbours (each would otherwise load the other's border before
+// it changes and ask for a re-visit), and every later group starts from
+// finished neighbours.
+__device__ __forceinline__ int64_t phase_tile(const KParams& kp, int64_t i) {
+  const int64_t tx = kp.phase_tx, ty = kp.phase_ty;
+  const int64_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
+  const int64_t n[4] = {ey * ex, ey * ox, oy * ex, oy * ox};
+  int p = 0;
+  while (p < 3 && i >= n[p]) i -= n[p++];
+  const int64_t w = (p & 1) ? ox : ex;
+  return (2 * (i / w) + (p >> 1)) * tx + 2 * (i % w) + (p & 1);
+}
+
 __device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, int q, int64_t i) {
   if (kp.list_mode) return kp.list_in[i * kp.nq + q];
   const int64_t c = (i / kp.chunk) * kp.nq + q;
   const int64_t t = c * kp.chunk + i % kp.chunk;
+  if (kp.phase_tx > 0) return phase_tile(kp, t);
   if (kp.order_mul == 1 && kp.order_add == 0) return t;
   return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);
 }

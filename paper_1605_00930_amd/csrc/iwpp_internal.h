@@ -88,6 +88,8 @@ struct KParams {
   int32_t nq;           // tile queues in use (1..kMaxQueues)
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
+  // four-phase first pass of a single image (0: off): its tile grid
+  int32_t phase_tx, phase_ty;
 };
 
 // Host-side launchers (iwpp_kernels.hip).  dtype: 0 = u8, 1 = i32.
