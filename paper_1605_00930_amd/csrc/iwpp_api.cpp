@@ -276,14 +276,17 @@ int Buffers::ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds) {
     (void)hipStreamSynchronize(stream_owner);
     (void)hipFree(state);
     (void)hipFree(visited);
+    (void)hipFree(tile_img);
     (void)hipFree(act[0]);
     (void)hipFree(act[1]);
     state = nullptr;
     visited = nullptr;
+    tile_img = nullptr;
     act[0] = act[1] = nullptr;
     int64_t cap = std::max<int64_t>(ntiles, 1024);
     HIP_TRY(hipMalloc(&state, cap * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&visited, cap));
+    HIP_TRY(hipMalloc(&tile_img, cap * sizeof(int32_t)));
     tiles_cap = cap;
     act_cap = 0;
   }
@@ -347,6 +350,7 @@ void Buffers::release() {
   (void)hipFree(queue);
   (void)hipFree(state);
   (void)hipFree(visited);
+  (void)hipFree(tile_img);
   (void)hipFree(act[0]);
   (void)hipFree(act[1]);
   (void)hipFree(descs);
@@ -485,7 +489,12 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
     rc = b.ensure(ntiles, kp.qcap * (uint32_t)kp.nq, nimg, false);
     if (rc) return rc;
     order_for(rp.order_seed, ntiles, &kp.order_mul, &kp.order_add);
-    if (rp.order_seed == 0 && nimg == 1 && !d_imgs) {
+    if (d_imgs) {
+      // batches: a table of each tile's image replaces the descriptor search
+      HIP_TRY(launch_tile_images(d_imgs, nimg, ntiles, b.tile_img, st));
+      kp.tile_img = b.tile_img;
+      if (rp.order_seed == 0) kp.phase_tx = -1;
+    } else if (rp.order_seed == 0) {
       kp.phase_tx = one.tiles_x;
       kp.phase_ty = one.tiles_y;
     }

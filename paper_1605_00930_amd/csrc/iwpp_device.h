@@ -89,6 +89,11 @@ __device__ __forceinline__ int find_image(const DevImage* imgs, int nimg, int64_
   return lo;
 }
 
+// The image of tile t of a batch: from the per-tile table when there is one.
+__device__ __forceinline__ int image_of(const KParams& kp, const DevImage* imgs, int64_t t) {
+  return kp.tile_img ? kp.tile_img[t] : find_image(imgs, kp.nimg, t);
+}
+
 __device__ __forceinline__ void add64(uint64_t* p, uint64_t v) {
   if (v) atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
@@ -159,8 +164,7 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
 // are seldom neighbours (each would otherwise load the other's border before
 // it changes and ask for a re-visit), and every later group starts from
 // finished neighbours.
-__device__ __forceinline__ int64_t phase_tile(const KParams& kp, int64_t i) {
-  const int64_t tx = kp.phase_tx, ty = kp.phase_ty;
+__device__ __forceinline__ int64_t phase_tile(int64_t tx, int64_t ty, int64_t i) {
   const int64_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
   const int64_t n[4] = {ey * ex, ey * ox, oy * ex, oy * ox};
   int p = 0;
@@ -169,11 +173,18 @@ __device__ __forceinline__ int64_t phase_tile(const KParams& kp, int64_t i) {
   return (2 * (i / w) + (p >> 1)) * tx + 2 * (i % w) + (p & 1);
 }
 
-__device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, int q, int64_t i) {
+__device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, const DevImage* imgs,
+                                                   int q, int64_t i) {
   if (kp.list_mode) return kp.list_in[i * kp.nq + q];
   const int64_t c = (i / kp.chunk) * kp.nq + q;
   const int64_t t = c * kp.chunk + i % kp.chunk;
-  if (kp.phase_tx > 0) return phase_tile(kp, t);
+  if (kp.phase_tx > 0) return phase_tile(kp.phase_tx, kp.phase_ty, t);
+  if (kp.phase_tx < 0) {
+    // a batch: the pass covers the images one after the other (tile ids),
+    // each in its own four phases
+    const DevImage& im = imgs[kp.tile_img[t]];
+    return im.tile_base + phase_tile(im.tiles_x, im.tiles_y, t - im.tile_base);
+  }
   if (kp.order_mul == 1 && kp.order_add == 0) return t;
   return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);
 }
@@ -228,14 +239,15 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 // the XCD, which a waiting worker must not do to the tiles others are
 // working on.
 static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
-                                     const uint8_t* visited, int q, int grid, uint32_t h,
+                                     const uint8_t* visited, const DevImage* imgs, int q,
+                                     int grid, uint32_t h,
                                      bool& first_pass, bool& ready, bool& first_visit) {
   const int64_t len = first_pass_len(kp, q);
   int v;
   first_pass = (int64_t)h < len;
   ready = first_pass;
   if (first_pass) {
-    v = (int)first_pass_tile(kp, q, h);
+    v = (int)first_pass_tile(kp, imgs, q, h);
   } else {
     int* slot = ring_slot(queue, kp, q, h, len);
     uint32_t nap = 1;
@@ -302,7 +314,8 @@ __device__ __forceinline__ bool take_request(uint32_t* word, uint32_t peeked) {
 // Take a tile id from queue q (using an already taken ticket if `pre` holds
 // one), or -1 when the launch is over.
 static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
-                                const uint8_t* visited, int q, int grid, uint32_t pre,
+                                const uint8_t* visited, const DevImage* imgs, int q, int grid,
+                                uint32_t pre,
                                 bool& first_pass, uint32_t& ticket, bool& ready,
                                 bool& first_visit) {
   first_pass = false;
@@ -313,7 +326,7 @@ static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const K
     pre = atomicAdd(&ctl->head[q].v, 1u);
   }
   ticket = pre;
-  return resolve_ticket(ctl, queue, kp, state, visited, q, grid, pre, first_pass, ready,
+  return resolve_ticket(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, ready,
                         first_visit);
 }
 
@@ -438,7 +451,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     int t = 0, fp = 0, fv = 0;
     if (lead) {
       bool first_pass = false, ready = false, first_visit = false;
-      t = queue_pop(ctl, queue, kp, state, visited, q, grid, pre, first_pass, last, ready,
+      t = queue_pop(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, last, ready,
                     first_visit);
       fp = first_pass ? 1 : 0;
       fv = first_visit ? 1 : 0;
@@ -451,7 +464,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     uint32_t c1 = (uint32_t)now();
     ws.t_idle += c1 - c0;
     if (t < 0) break;
-    const int k = imgs ? find_image(imgs, kp.nimg, t) : 0;
+    const int k = imgs ? image_of(kp, imgs, t) : 0;
     const DevImage im = imgs ? imgs[k] : one;
     const int64_t tl = (int64_t)t - im.tile_base;
     const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;

@@ -88,8 +88,10 @@ struct KParams {
   int32_t nq;           // tile queues in use (1..kMaxQueues)
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
-  // four-phase first pass of a single image (0: off): its tile grid
+  // four-phase first pass (see phase_tile): the tile grid of a single image,
+  // or phase_tx = -1 for a batch, each image on its own (0: off)
   int32_t phase_tx, phase_ty;
+  const int32_t* tile_img;  // batches: image index of every tile (or null)
 };
 
 // Host-side launchers (iwpp_kernels.hip).  dtype: 0 = u8, 1 = i32.
@@ -98,6 +100,8 @@ struct Variant {
   int dtype, conn, tile_h;
 };
 bool variant_supported(const Variant& v);
+hipError_t launch_tile_images(const DevImage* imgs, int nimg, int64_t ntiles, int32_t* out,
+                              hipStream_t st);
 hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
                        uint8_t* visited, uint8_t* active, hipStream_t st);
 hipError_t launch_persistent(const Variant& v, const DevImage& one, const DevImage* imgs,

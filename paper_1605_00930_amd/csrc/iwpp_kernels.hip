@@ -995,7 +995,7 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   const int64_t per = (kp.ntiles + 7) / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= kp.ntiles || !act_cur[t]) return;
-  const int k = imgs ? find_image(imgs, kp.nimg, t) : 0;
+  const int k = imgs ? image_of(kp, imgs, t) : 0;
   const DevImage im = imgs ? imgs[k] : one;
   const int64_t tl = t - im.tile_base;
   const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
@@ -1184,6 +1184,23 @@ int persistent_blocks_per_cu(const Variant& v) {
   IWPP_VARIANTS(X)
 #undef X
   return 0;
+}
+
+// Image index of every tile of a batch.
+__global__ void k_tile_images(const DevImage* imgs, int nimg, int64_t ntiles, int32_t* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride)
+    out[t] = find_image(imgs, nimg, t);
+}
+
+hipError_t launch_tile_images(const DevImage* imgs, int nimg, int64_t ntiles, int32_t* out,
+                              hipStream_t st) {
+  int64_t blocks = (ntiles + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_tile_images, dim3((unsigned)blocks), dim3(256), 0, st, imgs, nimg, ntiles,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,

@@ -36,6 +36,7 @@ struct Buffers {
   uint8_t* visited = nullptr;
   uint8_t* act[2] = {nullptr, nullptr};
   DevImage* descs = nullptr;
+  int32_t* tile_img = nullptr;  // batches: image index per tile (tiles_cap entries)
   int64_t tiles_cap = 0;
   int64_t act_cap = 0;
   uint32_t qcap_cap = 0;
