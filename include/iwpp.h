@@ -216,7 +216,7 @@ int iwpp_batch_destroy(iwpp_batch *b);
  * Times candidate parameter sets on one image and returns the fastest in
  * *best (bit-exactness of every candidate is the caller's to test).  The
  * search is coordinate descent: tile height x sweeps, then seed_queue, then
- * queue_waves, each stage from the best set so far (about 15 candidates,
+ * queue_waves, each stage from the best set so far (about 19 candidates,
  * four runs each).  The
  * marker is left unchanged: candidates run on a scratch copy.  Results are
  * remembered per (dtype, conn, size class) and used when params are NULL;

@@ -108,7 +108,9 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   Resolved r{};
   iwpp_params base{};
   base.tile_h = default_tile_h(dtype);
-  base.sweeps = dtype == IWPP_U8 ? 4 : 1;
+  // uint8 (fill-holes): a round of passes is cheap next to a scan and queue
+  // waves over a winding front, so a tile gets up to 16 rounds first
+  base.sweeps = dtype == IWPP_U8 ? 16 : 1;
   base.mode = 0;
   // uint8: fill-holes fronts wind through whole tiles, so re-visits go
   // straight to rounds of passes; int32 (h-dome): short fronts, few seeds
@@ -1031,7 +1033,7 @@ int iwpp_autotune(const iwpp_image* img, int dtype, int conn, iwpp_stream_t stre
     return r;
   };
   for (int th : tiles)
-    for (int sw : {1, 2, 4, -1}) {
+    for (int sw : {1, 2, 4, 8, 16, -1}) {
       iwpp_params p{};
       p.tile_h = th;
       p.sweeps = sw;
