@@ -289,6 +289,18 @@ static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, co
 
 constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 
+// Take a ticket of queue head *p (one lane).  The compiler combines the lanes
+// of an atomic with a wavefront-uniform address into one atomic and waits
+// for its result at once, to hand each lane its share; an address offset
+// that it cannot prove uniform (a zero written by an asm move) keeps the
+// plain atomic, whose round trip then overlaps the work before the ticket
+// is used.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t* p) {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return atomicAdd(p + z, 1u);
+}
+
 // Mid-visit requests.  peek_request() reads the state word of the tile a
 // wavefront is visiting (lane 0; the result is used later, so the read's
 // round trip overlaps work); take_request() with that value returns true if
@@ -323,7 +335,7 @@ static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const K
   first_visit = false;
   if (pre == kNoTicket) {
     if (ld_rlx_u32(&ctl->done.v)) return -1;
-    pre = atomicAdd(&ctl->head[q].v, 1u);
+    pre = take_ticket(&ctl->head[q].v);
   }
   ticket = pre;
   return resolve_ticket(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, ready,
@@ -355,7 +367,7 @@ static __device__ __forceinline__ uint32_t prefetch_ticket(DevCtl* ctl, const KP
   // the done flag.
   const int64_t per_queue = grid / kp.nq + 1;
   if (!backlog && (int64_t)last + 2 * per_queue >= first_pass_len(kp, q)) return kNoTicket;
-  return atomicAdd(&ctl->head[q].v, 1u);
+  return take_ticket(&ctl->head[q].v);
 }
 
 // Publish the end of a visit of tile t (whole wavefront, once the tile's

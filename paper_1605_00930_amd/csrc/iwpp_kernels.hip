@@ -295,29 +295,28 @@ struct Tile {
 
   __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
                                uint32_t flip) {
-    const gptr<T> gJ = (gptr<T>)im.J;
-    const int64_t gx = x0 + lane();
-    const bool col_in = gx < im.W;
+    const bool col_in = x0 + lane() < im.W;
+    constexpr int NR = TH < 64 ? TH : 64;
     for (int g = 0; g < TH; g += 64) {
       // lane k reports row g + k; the set bits are the rows to write back
       const unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
-      // eight rows at a time: their LDS reads go out together, then the
-      // stores of the dirty ones
-      constexpr int GR = 8;
-      constexpr int NR = TH < 64 ? TH : 64;
-#pragma unroll 1
-      for (int yb = 0; yb < NR; yb += GR) {
-        const uint32_t bits = (uint32_t)(rows >> yb) & ((1u << GR) - 1);
-        if (!bits) continue;
-        int v[GR];
+      if (!rows) continue;
+      // Every row's value is read from LDS before the first store: an LDS
+      // read into a register that an outstanding store still reads would
+      // make the store wait for completion (a store reads its registers
+      // after it issues), so reads between stores serialize them.
+      int v[NR];
 #pragma unroll
-        for (int k = 0; k < GR; ++k) v[k] = (int)s.J[G::at(g + yb + k, lane())];
+      for (int k = 0; k < NR; ++k) v[k] = (int)s.J[G::at(g + k, lane())];
+      // one pointer, stepped row by row (the empty asm keeps the compiler
+      // from holding every row's address in registers at once)
+      gptr<T> row = (gptr<T>)im.J + (y0 + g) * im.ld + x0 + lane();
+      const int64_t rows_in = im.H - (y0 + g);
 #pragma unroll
-        for (int k = 0; k < GR; ++k) {
-          const int64_t gy = y0 + g + yb + k;
-          if (((bits >> k) & 1u) && gy < im.H && col_in)
-            st_coherent(&gJ[gy * im.ld + gx], out((T)v[k], flip));
-        }
+      for (int k = 0; k < NR; ++k) {
+        if (((rows >> k) & 1ull) && k < rows_in && col_in) st_coherent(row, out((T)v[k], flip));
+        row += im.ld;
+        asm volatile("" : "+v"(row));
       }
     }
   }
