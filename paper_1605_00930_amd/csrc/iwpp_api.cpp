@@ -320,6 +320,31 @@ int Buffers::ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds) {
   return IWPP_OK;
 }
 
+int Buffers::ensure_cols(int64_t bytes) {
+  if (bytes <= cols_cap) return IWPP_OK;
+  (void)hipStreamSynchronize(stream_owner);
+  (void)hipFree(cols);
+  cols = nullptr;
+  cols_cap = 0;
+  HIP_TRY(hipMalloc(&cols, (size_t)bytes));
+  cols_cap = bytes;
+  return IWPP_OK;
+}
+
+// Packed side columns of a persistent reconstruction launch, kept in the
+// workspace.  Nothing fills them up front: a tile writes its own on its first
+// visit, and a neighbour reads them only once that visit is complete.
+static int setup_cols(Buffers& b, const Variant& v, int64_t ntiles, KParams& kp) {
+  if (v.dtype == kDtypeEdt) return IWPP_OK;
+  const int64_t esz = v.dtype == IWPP_U8 ? 1 : 4;
+  const int64_t n = ntiles * 2 * v.tile_h;
+  const int rc = b.ensure_cols_for(v.dtype, v.tile_h, ntiles);
+  if (rc) return rc;
+  kp.colI = b.cols;
+  kp.colJ = (char*)b.cols + n * esz;
+  return IWPP_OK;
+}
+
 int Buffers::ensure_bands(int64_t ntiles) {
   if (ntiles <= band_cap) return IWPP_OK;
   (void)hipStreamSynchronize(stream_owner);
@@ -353,6 +378,7 @@ void Buffers::release() {
   (void)hipFree(state);
   (void)hipFree(visited);
   (void)hipFree(tile_img);
+  (void)hipFree(cols);
   (void)hipFree(act[0]);
   (void)hipFree(act[1]);
   (void)hipFree(descs);
@@ -392,6 +418,7 @@ int enqueue_bands(Buffers& b, const Variant& v, const Resolved& rp, const DevIma
   if (rc) return rc;
   rc = b.ensure(ntiles, kp.qcap * (uint32_t)kp.nq, nimg, false);
   if (!rc) rc = b.ensure_bands(ntiles);
+  if (!rc) rc = setup_cols(b, v, ntiles, kp);
   if (rc) return rc;
   order_for(rp.order_seed, ntiles, &kp.order_mul, &kp.order_add);
   // value range of the marker, in the tile order
@@ -500,6 +527,8 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
       kp.phase_tx = one.tiles_x;
       kp.phase_ty = one.tiles_y;
     }
+    rc = setup_cols(b, v, ntiles, kp);
+    if (rc) return rc;
     HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, st));
     b.timed = false;
     if (rp.timing) {
@@ -898,6 +927,8 @@ int iwpp_batch_create(const iwpp_image* imgs, int32_t n, int dtype, int conn, ui
   KParams kp{};
   if (!rc) rc = plan_queues(b->v, b->rp, base, n, b->h[0], &grid, &kp);
   if (!rc) rc = b->buf.ensure(base, kp.qcap * (uint32_t)kp.nq, n, false);
+  // sized now: a graph capture of the launch must not allocate
+  if (!rc) rc = b->buf.ensure_cols_for(b->v.dtype, b->v.tile_h, base);
   if (!rc) {
     e = hipMemcpy(b->buf.descs, b->h.data(), n * sizeof(DevImage), hipMemcpyHostToDevice);
     if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(descs)");

@@ -241,7 +241,7 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
                                      const uint8_t* visited, const DevImage* imgs, int q,
                                      int grid, uint32_t h,
-                                     bool& first_pass, bool& ready, bool& first_visit) {
+                                     bool& first_pass, bool& ready, int& vbits) {
   const int64_t len = first_pass_len(kp, q);
   int v;
   first_pass = (int64_t)h < len;
@@ -278,12 +278,18 @@ static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, co
   // pending -> running.  A neighbour that asked for this visit finished its
   // marker stores before its request reached the state word, so once the
   // exchange is complete, the marker reads that follow see them.  The
-  // visited flag (written by the tile's last owner before it released the
-  // tile) is read in the same round trip.
+  // visited flags of the tile (written by its last owner before it released
+  // it) and of the tiles on either side (whether their packed side columns
+  // are written yet) are read in the same round trip.
   __hip_atomic_exchange(&state[v], TS_RUNNING, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint8_t seen = ld_coherent(&visited[v]);
+  uint8_t sl = 0, sr = 0;
+  if (kp.colJ) {
+    if (v > 0) sl = ld_coherent(&visited[v - 1]);
+    if (v + 1 < kp.ntiles) sr = ld_coherent(&visited[v + 1]);
+  }
   drain_memory();
-  first_visit = seen == 0;
+  vbits = (seen == 0 ? 1 : 0) | (sl ? 2 : 0) | (sr ? 4 : 0);
   return v;
 }
 
@@ -329,17 +335,17 @@ static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const K
                                 const uint8_t* visited, const DevImage* imgs, int q, int grid,
                                 uint32_t pre,
                                 bool& first_pass, uint32_t& ticket, bool& ready,
-                                bool& first_visit) {
+                                int& vbits) {
   first_pass = false;
   ready = false;
-  first_visit = false;
+  vbits = 0;
   if (pre == kNoTicket) {
     if (ld_rlx_u32(&ctl->done.v)) return -1;
     pre = take_ticket(&ctl->head[q].v);
   }
   ticket = pre;
   return resolve_ticket(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, ready,
-                        first_visit);
+                        vbits);
 }
 
 // Gray-level bands: remember that tile t has work of class c for a later
@@ -462,11 +468,10 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     uint32_t c0 = (uint32_t)now();
     int t = 0, fp = 0, fv = 0;
     if (lead) {
-      bool first_pass = false, ready = false, first_visit = false;
+      bool first_pass = false, ready = false;
       t = queue_pop(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, last, ready,
-                    first_visit);
+                    fv);
       fp = first_pass ? 1 : 0;
-      fv = first_visit ? 1 : 0;
       backlog = !first_pass && ready;
       pre = kNoTicket;
     }
@@ -502,10 +507,12 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       }
     }
     ws.visits++;
-    const bool first = fv != 0;
+    const bool first = (fv & 1) != 0;
+    // packed side columns of the left / right neighbour are written (bit 0 / 1)
+    const int sides = fv >> 1;
     VisitStats vs;
     bool hit = false;
-    const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
+    const bool viol = TP::load(s, im, y0, x0, first, kp, t, tx, sides);
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
     if (lead) pre = prefetch_ticket(ctl, kp, q, grid, last, backlog);
@@ -516,11 +523,11 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     uint32_t c3 = c2;
     for (;;) {
       const bool more = TP::solve(s, y0, x0, kp.sweeps, seeded, kp.seed_queue_max,
-                                  kp.queue_waves, kp.spin_limit, vs, hit, &state[t], im, kp.flip,
-                                  resume, early);
+                                  kp.queue_waves, kp.spin_limit, vs, hit, &state[t], im, kp, t,
+                                  tx, sides, resume, early);
       uint32_t c3a = (uint32_t)now();
       ws.t_solve += c3a - c3;
-      TP::store(s, im, y0, x0, kp.flip);
+      TP::store(s, im, y0, x0, kp, t, first);
       int amax = 0;
       const uint32_t act = TP::activation_mask(s, y0, x0, kp.band >= 0, amax);
       int cls = 0;
@@ -533,13 +540,15 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       ws.add(vs);
       vs = VisitStats();
       if (lead) {
-        if (first) st_coherent(&visited[t], (uint8_t)1);
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
       hit = false;
       // the write-back is complete before anyone is told about it
       drain_memory();
+      // ... and, with it, this tile's packed side columns: only now may a
+      // neighbour see the visited flag and read them
+      if (lead && first) st_coherent(&visited[t], (uint8_t)1);
       // with `more` the border raised a neighbour before the tile's fixed
       // point: the requests go out now and the rounds go on
       const bool release = !(TP::kStreaming && more);
@@ -561,7 +570,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       }
       if (res != 1) break;
       // a neighbour changed while this tile ran: reload the halo, continue
-      TP::reload_halo(s, im, y0, x0, kp.flip);
+      TP::reload_halo(s, im, y0, x0, kp, t, tx, sides);
       c3 = (uint32_t)now();
       ws.t_load += c3 - c4;
       seeded = true;

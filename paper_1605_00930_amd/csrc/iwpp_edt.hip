@@ -77,7 +77,7 @@ struct EdtTile {
   // Stage the sites of the tile and its halo (coherent loads: neighbours on
   // other XCDs write them); pixels outside the image have no site.
   __device__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool,
-                              uint32_t) {
+                              const KParams&, int64_t, int64_t, int) {
     const gptr<const uint32_t> gS = (gptr<const uint32_t>)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     for (int e = lane(); e < G::ROWS * (TW + 2); e += 64) {
@@ -111,7 +111,7 @@ struct EdtTile {
   }
 
   __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
-                                     uint32_t) {
+                                     const KParams&, int64_t, int64_t, int) {
     const gptr<const uint32_t> gS = (gptr<const uint32_t>)im.J;
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     for (int e = lane(); e < G::HALO; e += 64) {
@@ -139,7 +139,7 @@ struct EdtTile {
   }
 
   __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
-                               uint32_t) {
+                               const KParams&, int64_t, bool) {
     const gptr<uint32_t> gS = (gptr<uint32_t>)im.J;
     const int64_t gx = x0 + lane();
     const bool col_in = gx < im.W;
@@ -299,7 +299,7 @@ struct EdtTile {
   static constexpr bool kStreaming = false;
   __device__ static bool solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
                                uint32_t iter_limit, VisitStats& vs, bool& hit_limit, uint32_t*,
-                               const DevImage&, uint32_t, bool, bool) {
+                               const DevImage&, const KParams&, int64_t, int64_t, int, bool, bool) {
     // passes down, up, right, left, round after round, until four in a row
     // change nothing: those four saw the same tile in every direction
     int quiet = 0;

@@ -92,6 +92,11 @@ struct KParams {
   // or phase_tx = -1 for a batch, each image on its own (0: off)
   int32_t phase_tx, phase_ty;
   const int32_t* tile_img;  // batches: image index of every tile (or null)
+  // packed side columns of I and J (column 0 and TW - 1 of every tile, row
+  // after row), written by each tile from its first visit on (null: halo
+  // columns are read from the image)
+  const void* colI;
+  void* colJ;
 };
 
 // Host-side launchers (iwpp_kernels.hip).  dtype: 0 = u8, 1 = i32.
@@ -102,6 +107,7 @@ struct Variant {
 bool variant_supported(const Variant& v);
 hipError_t launch_tile_images(const DevImage* imgs, int nimg, int64_t ntiles, int32_t* out,
                               hipStream_t st);
+
 hipError_t launch_init(const KParams& kp, DevCtl* ctl, int* queue, uint32_t* state,
                        uint8_t* visited, uint8_t* active, hipStream_t st);
 hipError_t launch_persistent(const Variant& v, const DevImage& one, const DevImage* imgs,

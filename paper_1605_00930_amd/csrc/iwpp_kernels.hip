@@ -132,22 +132,85 @@ struct Tile {
   }
 
   // ---------------------------------------------------------- load / store
-  // Stage the tile at (y0, x0) and its halo.  Pixels outside the image
-  // become the lowest value in both I and J: they can neither give nor take
-  // a value.  J is clamped to I on load (a clamped pixel's row is marked
-  // dirty so that the clamp reaches memory); returns true if a first visit
-  // saw J > I inside the tile.
-  __device__ __forceinline__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
-                              uint32_t flip) {
+  // Packed side columns.  A launch that keeps them (kp.colJ, kp.colI) holds,
+  // for every tile t, its column 0 and its column TW - 1 row after row:
+  // entry (t * 2 + side) * TH + r.  A tile reads its halo columns from its
+  // neighbours' entries (one contiguous run per side) instead of one pixel
+  // from each of TH rows, which costs a whole cache line per row; its owner
+  // rewrites them with the tile's dirty rows.  Entries hold memory values
+  // (before the complement of an erosion), like the image.
+  __device__ static int64_t side_at(int64_t t, int side) { return (t * 2 + side) * TH; }
+
+  // Stage the tile at (y0, x0) (tile t, column tx of its image's tile grid)
+  // and its halo.  Pixels outside the image become the lowest value in both
+  // I and J: they can neither give nor take a value.  J is clamped to I on
+  // load (a clamped pixel's row is marked dirty so that the clamp reaches
+  // memory); returns true if a first visit saw J > I inside the tile.
+  __device__ __forceinline__ static bool load(L& s, const DevImage& im, int64_t y0, int64_t x0,
+                                              bool first, const KParams& kp, int64_t t,
+                                              int64_t tx, int sides) {
     // almost every tile lies inside the image with its halo: its loads need
     // no bounds checks and its two row batches are unrolled
     const bool inner = y0 >= 1 && y0 + TH < im.H && x0 >= 1 && x0 + TW < im.W;
-    return inner ? load_t<true>(s, im, y0, x0, first, flip)
-                 : load_t<false>(s, im, y0, x0, first, flip);
+    return inner ? load_t<true>(s, im, y0, x0, first, kp, t, tx, sides)
+                 : load_t<false>(s, im, y0, x0, first, kp, t, tx, sides);
   }
+
+  // Halo side entry e of a tile: e < TH the left halo column of row e,
+  // e < 2 TH the right one of row e - TH, then the four corners (top left,
+  // top right, bottom left, bottom right), at (y, x) in halo coordinates
+  // (-1 .. TH, -1 .. TW).
+  __device__ __forceinline__ static void side_pos(int e, int& y, int& x) {
+    if (e < 2 * TH) {
+      y = e >= TH ? e - TH : e;
+      x = e >= TH ? TW : -1;
+    } else {
+      y = ((e - 2 * TH) & 2) ? TH : -1;
+      x = ((e - 2 * TH) & 1) ? TW : -1;
+    }
+  }
+  // Loads side entry e: returns whether the pixel lies in the image; the raw
+  // J and I values go to j and i.  A halo column comes from the neighbour's
+  // packed side column when `sides` says it is written (bit 0 left, bit 1
+  // right: the neighbour's first visit is complete), else from the image.
   template <bool INNER>
-  __device__ __forceinline__ static bool load_t(L& s, const DevImage& im, int64_t y0, int64_t x0, bool first,
-                                uint32_t flip) {
+  __device__ __forceinline__ static bool side_load(const DevImage& im, int64_t y0, int64_t x0,
+                                                   const KParams& kp, int64_t t, int64_t tx,
+                                                   int sides, int e, int& j, int& i) {
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    const gptr<const T> gI = (gptr<const T>)im.I;
+    int y, x;
+    side_pos(e, y, x);
+    if (e < 2 * TH) {
+      const int side = e >= TH;
+      const bool nb = side ? tx + 1 < im.tiles_x : tx > 0;
+      if (!(INNER || (nb && y0 + y < im.H))) return false;
+      if ((sides >> side) & 1) {
+        // the neighbour's own side facing this tile
+        const int64_t k = side_at(side ? t + 1 : t - 1, side ? 0 : 1) + y;
+        // both written during the launch, possibly under another XCD's L2:
+        // coherent loads, like the marker
+        j = (int)ld_coherent(&((gptr<const T>)kp.colJ)[k]);
+        i = (int)ld_coherent(&((gptr<const T>)kp.colI)[k]);
+      } else {
+        const int64_t a = (y0 + y) * im.ld + x0 + x;
+        j = (int)ld_coherent(&gJ[a]);
+        i = (int)gI[a];
+      }
+      return true;
+    }
+    const int64_t gy = y0 + y, gx = x0 + x;
+    if (!(INNER || (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W))) return false;
+    j = (int)ld_coherent(&gJ[gy * im.ld + gx]);
+    i = (int)gI[gy * im.ld + gx];
+    return true;
+  }
+
+  template <bool INNER>
+  __device__ __forceinline__ static bool load_t(L& s, const DevImage& im, int64_t y0, int64_t x0,
+                                                bool first, const KParams& kp, int64_t t,
+                                                int64_t tx, int sides) {
+    const uint32_t flip = kp.flip;
     // image rows live in global memory: address-space-1 pointers give
     // global_load instructions, which (unlike flat ones) leave the LDS
     // counter alone
@@ -160,15 +223,16 @@ struct Tile {
     // the batch, so no load waits for its own data; a pixel outside the image
     // starts as the raw encoding of LO
     const int lo_raw = in((T)LO, flip);
-    // Lanes 0..63 cover padded columns 0..63 (the left halo column and tile
-    // columns 0..62), B rows per batch; padded columns 64 and 65 (tile column
-    // 63 and the right halo column) of all rows are spread over the lanes and
-    // issued with the first batch.  Two batches cover the tile.
-    constexpr int B = G::ROWS / 2 + 1 < 33 ? G::ROWS / 2 + 1 : 33;
-    constexpr int NE = 2 * G::ROWS;
+    // Rows -1 .. TH of the tile's own columns, one lane per column, B rows
+    // per batch (each row is whole cache lines of this tile).  The halo
+    // columns and corners (side entries, see side_load) are spread over the
+    // lanes and issued with the first batch.  Two batches cover a tile of
+    // up to 64 rows; taller tiles take batches of 22 rows (registers).
+    constexpr int B = G::ROWS <= 66 ? G::ROWS / 2 + 1 : 22;
+    constexpr int NE = 2 * TH + 4;
     constexpr int K = (NE + 63) / 64;
-    const int64_t gx = x0 + lane() - 1;
-    const bool c_in = gx >= 0 && gx < im.W;
+    const int64_t gx = x0 + lane();
+    const bool c_in = gx < im.W;
     int ej[K], ei[K];
     auto batch = [&](const int yb) {
       int j[B], i[B];
@@ -188,13 +252,8 @@ struct Tile {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const int e = lane() + 64 * k;
-          const int yy = e >> 1, c = 64 + (e & 1);
-          const int64_t ey = y0 + yy - 1, ex = x0 + c - 1;
           ej[k] = ei[k] = lo_raw;
-          if (e < NE && (INNER || (ey >= 0 && ey < im.H && ex < im.W))) {
-            ej[k] = (int)ld_coherent(&gJ[ey * im.ld + ex]);
-            ei[k] = (int)gI[ey * im.ld + ex];
-          }
+          if (e < NE) side_load<INNER>(im, y0, x0, kp, t, tx, sides, e, ej[k], ei[k]);
         }
       }
 #pragma unroll
@@ -204,14 +263,14 @@ struct Tile {
         int a = in((T)j[k], flip);
         const int b = in((T)i[k], flip);
         if (a > b) {
-          if (yy >= 1 && yy <= TH && lane() >= 1) {
+          if (yy >= 1 && yy <= TH) {
             viol = viol || first;
             s.rowdirty[yy - 1] = 1;  // the clamped value must reach memory
           }
           a = b;
         }
-        s.J[yy * G::P + lane()] = (T)a;
-        s.I[yy * G::P + lane()] = (T)b;
+        s.J[yy * G::P + lane() + 1] = (T)a;
+        s.I[yy * G::P + lane() + 1] = (T)b;
       }
     };
     if (INNER && G::ROWS <= 2 * B) {
@@ -221,22 +280,17 @@ struct Tile {
 #pragma unroll 1
       for (int yb = 0; yb < G::ROWS; yb += B) batch(yb);
     }
+    // side entries: halo pixels only, clamped but never dirty
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int e = lane() + 64 * k;
       if (e >= NE) continue;
-      const int yy = e >> 1, c = 64 + (e & 1);
-      int a = in((T)ej[k], flip);
+      int y, x;
+      side_pos(e, y, x);
       const int b = in((T)ei[k], flip);
-      if (a > b) {
-        if (yy >= 1 && yy <= TH && c == 64) {
-          viol = viol || first;
-          s.rowdirty[yy - 1] = 1;
-        }
-        a = b;
-      }
-      s.J[yy * G::P + c] = (T)a;
-      s.I[yy * G::P + c] = (T)b;
+      const int a = imin(in((T)ej[k], flip), b);
+      s.J[G::at(y, x)] = (T)a;
+      s.I[G::at(y, x)] = (T)b;
     }
     wsync();
     snapshot_border(s);
@@ -244,7 +298,7 @@ struct Tile {
     return __ballot(viol) != 0;
   }
 
-  __device__ static void snapshot_border(L& s) {
+  __device__ __forceinline__ static void snapshot_border(L& s) {
     s.b_top[lane()] = s.J[G::at(0, lane())];
     s.b_bot[lane()] = s.J[G::at(TH - 1, lane())];
     for (int y = lane(); y < TH; y += 64) {
@@ -256,47 +310,65 @@ struct Tile {
   // Re-read the halo of J for a re-run after a release that found a
   // request; the tile's own pixels in LDS are current because this
   // wavefront is their only writer.
-  __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0, int64_t x0,
-                                     uint32_t flip) {
+  __device__ __forceinline__ static void reload_halo(L& s, const DevImage& im, int64_t y0,
+                                                     int64_t x0, const KParams& kp, int64_t t,
+                                                     int64_t tx, int sides) {
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
-    refresh_halo(s, im, y0, x0, flip);
+    refresh_halo(s, im, y0, x0, kp, t, tx, sides);
     snapshot_border(s);
     wsync();
   }
 
-  // Re-read the halo of J (and nothing else).
+  // Re-read the halo of J (and nothing else): the rows above and below the
+  // tile's own columns, then the side entries.
   __device__ __forceinline__ static void refresh_halo(L& s, const DevImage& im, int64_t y0,
-                                                      int64_t x0, uint32_t flip) {
-    const T* __restrict__ gJ = (const T*)im.J;
-    for (int e = lane(); e < G::HALO; e += 64) {
-      int y, x;
-      if (e < TW + 2) {
-        y = -1;
-        x = e - 1;
-      } else if (e < 2 * (TW + 2)) {
-        y = TH;
-        x = e - (TW + 2) - 1;
-      } else if (e < 2 * (TW + 2) + TH) {
-        y = e - 2 * (TW + 2);
-        x = -1;
-      } else {
-        y = e - 2 * (TW + 2) - TH;
-        x = TW;
+                                                      int64_t x0, const KParams& kp, int64_t t,
+                                                      int64_t tx, int sides) {
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    constexpr int NE = 2 * TH + 4;
+    const int64_t gx = x0 + lane();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int y = h ? TH : -1;
+      const int64_t gy = y0 + y;
+      if (gy >= 0 && gy < im.H && gx < im.W) {
+        const int j = in(ld_coherent(&gJ[gy * im.ld + gx]), kp.flip);
+        s.J[G::at(y, lane())] = (T)imin(j, iv(s, y, lane()));
       }
-      const int64_t gy = y0 + y, gx = x0 + x;
-      if (gy >= 0 && gy < im.H && gx >= 0 && gx < im.W) {
-        const int i = iv(s, y, x);
-        const int j = in(ld_coherent(&gJ[gy * im.ld + gx]), flip);
-        s.J[G::at(y, x)] = (T)imin(j, i);
-      }
+    }
+    for (int e = lane(); e < NE; e += 64) {
+      int y, x, j, i;
+      side_pos(e, y, x);
+      if (side_load<false>(im, y0, x0, kp, t, tx, sides, e, j, i))
+        s.J[G::at(y, x)] = (T)imin(in((T)j, kp.flip), iv(s, y, x));
     }
     wsync();
   }
 
-  __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0, int64_t x0,
-                               uint32_t flip) {
+  // Write back the dirty rows, and their side pixels into the packed side
+  // columns when the launch keeps them: every row's on the tile's first
+  // visit (nothing wrote them before), with the side pixels of I.
+  __device__ __forceinline__ static void store(const L& s, const DevImage& im, int64_t y0,
+                                               int64_t x0, const KParams& kp, int64_t t,
+                                               bool first) {
+    const uint32_t flip = kp.flip;
     const bool col_in = x0 + lane() < im.W;
     constexpr int NR = TH < 64 ? TH : 64;
+    // side entry e: column 0 of row e (e < TH), column TW - 1 of row e - TH;
+    // read before the first store, like the rows (see below)
+    constexpr int KS = (2 * TH + 63) / 64;
+    int sv[KS];
+    bool sw[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int e = lane() + 64 * k;
+      const int side = e >= TH, r = side ? e - TH : e, x = side ? TW - 1 : 0;
+      sw[k] = kp.colJ && e < 2 * TH && (first || s.rowdirty[r]) && y0 + r < im.H &&
+              x0 + x < im.W;
+      sv[k] = sw[k] ? (int)s.J[G::at(r, x)] : 0;
+      if (first && sw[k])
+        st_coherent(&((gptr<T>)kp.colI)[side_at(t, side) + r], out(s.I[G::at(r, x)], flip));
+    }
     for (int g = 0; g < TH; g += 64) {
       // lane k reports row g + k; the set bits are the rows to write back
       const unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
@@ -318,6 +390,12 @@ struct Tile {
         row += im.ld;
         asm volatile("" : "+v"(row));
       }
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int e = lane() + 64 * k;
+      const int side = e >= TH, r = side ? e - TH : e;
+      if (sw[k]) st_coherent(&((gptr<T>)kp.colJ)[side_at(t, side) + r], out((T)sv[k], flip));
     }
   }
 
@@ -649,7 +727,8 @@ struct Tile {
   enum { kRoundsLeft = 0, kFixed = 1, kEarly = 2 };
   __device__ static int sweep_rounds(L& s, int budget, int first_pass, VisitStats& vs,
                                      uint32_t* watch, const DevImage& im, int64_t y0, int64_t x0,
-                                     uint32_t flip, bool early) {
+                                     const KParams& kp, int64_t t, int64_t tx, int sides,
+                                     bool early) {
     int quiet = 0, k = 0;
     int res = kRoundsLeft;
     for (; k < 4 * budget && quiet < 4; ++k) {
@@ -665,7 +744,7 @@ struct Tile {
           break;
         }
         if (take_request(watch, peek_request(watch))) {
-          refresh_halo(s, im, y0, x0, flip);
+          refresh_halo(s, im, y0, x0, kp, t, tx, sides);
           quiet = 0;
         }
       }
@@ -880,7 +959,8 @@ struct Tile {
   __device__ __forceinline__ static bool solve(L& s, int64_t y0, int64_t x0, int sweeps, bool seeded,
                                int seed_queue_max, uint32_t waves, uint32_t iter_limit,
                                VisitStats& vs, bool& hit_limit, uint32_t* watch,
-                               const DevImage& im, uint32_t flip, bool resume, bool early) {
+                               const DevImage& im, const KParams& kp, int64_t t, int64_t tx,
+                               int sides, bool resume, bool early) {
     int budget = sweeps;
     int first_pass = 0;
     if (resume) {
@@ -894,7 +974,8 @@ struct Tile {
       if (budget < 1) budget = 1;
     }
     for (uint32_t guard = 0;; ++guard) {
-      const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, flip, early);
+      const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, kp, t, tx, sides,
+                                 early);
       if (r == kFixed) return false;
       if (r == kEarly) return true;
       const int n = scan_receivers(s);
@@ -908,7 +989,7 @@ struct Tile {
     }
   }
 
-  __device__ static void clear_dirty(L& s) {
+  __device__ __forceinline__ static void clear_dirty(L& s) {
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     wsync();
   }
@@ -1002,10 +1083,10 @@ __global__ __launch_bounds__(64) void k_round(DevImage one, const DevImage* __re
   const bool first = visited[t] == 0;
   VisitStats vs;
   bool hit = false;
-  const bool viol = TP::load(s, im, y0, x0, first, kp.flip);
+  const bool viol = TP::load(s, im, y0, x0, first, kp, t, tx, 0);
   TP::solve(s, y0, x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves, kp.spin_limit,
-            vs, hit, nullptr, im, kp.flip, false, false);
-  TP::store(s, im, y0, x0, kp.flip);
+            vs, hit, nullptr, im, kp, t, tx, 0, false, false);
+  TP::store(s, im, y0, x0, kp, t, first);
   int amax = 0;
   const uint32_t act = TP::activation_mask(s, y0, x0, false, amax);
   if (threadIdx.x == 0) {

@@ -37,6 +37,8 @@ struct Buffers {
   uint8_t* act[2] = {nullptr, nullptr};
   DevImage* descs = nullptr;
   int32_t* tile_img = nullptr;  // batches: image index per tile (tiles_cap entries)
+  void* cols = nullptr;         // packed side columns of I and J
+  int64_t cols_cap = 0;         // bytes
   int64_t tiles_cap = 0;
   int64_t act_cap = 0;
   uint32_t qcap_cap = 0;
@@ -54,6 +56,11 @@ struct Buffers {
   int64_t band_cap = 0;
   int ensure(int64_t ntiles, uint32_t qcap, int nimg, bool rounds);
   int ensure_bands(int64_t ntiles);
+  int ensure_cols(int64_t bytes);
+  // ensure_cols for a reconstruction launch of `ntiles` tiles of variant v
+  int ensure_cols_for(int dtype, int tile_h, int64_t ntiles) {
+    return ensure_cols(2 * ntiles * 2 * tile_h * (dtype == 0 ? 1 : 4));
+  }
   void release();
 };
 

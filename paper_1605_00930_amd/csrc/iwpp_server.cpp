@@ -128,6 +128,7 @@ int launch_batch(iwpp_server* srv, Slot* s, std::vector<Request*>& batch) {
   KParams kp{};
   int rc = plan_queues(srv->v, srv->rp, base, n, s->staging[0], &grid, &kp);
   if (!rc) rc = s->buf.ensure(base, kp.qcap * (uint32_t)kp.nq, n, false);
+  if (!rc) rc = s->buf.ensure_cols_for(srv->v.dtype, srv->v.tile_h, base);
   if (rc) return rc;
   if (hipMemcpyAsync(s->buf.descs, s->staging, n * sizeof(DevImage), hipMemcpyHostToDevice,
                      s->st) != hipSuccess)
