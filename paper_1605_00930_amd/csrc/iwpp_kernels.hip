@@ -90,8 +90,8 @@ struct Geo {
 template <typename T, int TH>
 struct Lds {
   using G = Geo<T, TH>;
-  T J[G::ROWS * G::P];
-  T I[G::ROWS * G::P];
+  alignas(16) T J[G::ROWS * G::P];
+  alignas(16) T I[G::ROWS * G::P];
   uint16_t q[2][G::QCAP];
   uint32_t claim[G::NWORDS];  // pixels already in the next queue
   T b_top[TW], b_bot[TW], b_left[TH], b_right[TH];  // border as loaded
@@ -369,10 +369,61 @@ struct Tile {
       if (first && sw[k])
         st_coherent(&((gptr<T>)kp.colI)[side_at(t, side) + r], out(s.I[G::at(r, x)], flip));
     }
+    // uint8 rows are written four pixels to a lane when the image allows
+    // 4-byte accesses there (a 64-byte row is then 16 lanes, four rows to an
+    // instruction) instead of one byte per lane and row
+    // (64-row tiles; taller ones keep within their register budget with bytes)
+    const bool wide = sizeof(T) == 1 && TH <= 64 && ((uintptr_t)im.J % 4) == 0 &&
+                      (im.ld % 4) == 0 && x0 + TW <= im.W;
     for (int g = 0; g < TH; g += 64) {
       // lane k reports row g + k; the set bits are the rows to write back
       const unsigned long long rows = __ballot(g + lane() < TH && s.rowdirty[g + lane()]);
       if (!rows) continue;
+      if constexpr (sizeof(T) == 1) {
+        if (TH <= 64 && wide) {
+          // lane l: columns 4 (l % 16) .. + 3 of rows 4 q + l / 16, eight
+          // quads of rows at a time
+          constexpr int NQ = NR / 4;
+          const int c4 = (lane() & 15) * 4, rs = lane() >> 4;
+          gptr<uint32_t> row = (gptr<uint32_t>)((gptr<T>)im.J + (y0 + g + rs) * im.ld + x0 + c4);
+          const uint32_t fw = flip ? 0xFFFFFFFFu : 0u;
+          // this lane's rows: bit q for row 4 q + rs, dirty and inside the image
+          const int64_t rows_in = im.H - (y0 + g);
+          uint32_t mine = 0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            mine |= (uint32_t)(((rows >> (4 * q)) >> rs) & 1ull & (4 * q + rs < rows_in)) << q;
+#pragma unroll
+          for (int q0 = 0; q0 < NQ; q0 += 8) {
+            uint32_t w[8];
+            // the four pixels start one byte past a 4-byte boundary in LDS
+            // (the halo column comes first): two aligned words and a shift
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const uint32_t* a = (const uint32_t*)&s.J[G::at(g + 4 * (q0 + q) + rs, c4) - 1];
+              w[q] = __builtin_amdgcn_alignbyte(a[1], a[0], 1);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              if ((mine >> (q0 + q)) & 1u) st_coherent(row, w[q] ^ fw);
+              row = (gptr<uint32_t>)((gptr<T>)row + 4 * im.ld);
+              asm volatile("" : "+v"(row));
+            }
+          }
+          continue;
+        }
+        // other uint8 rows (a pitch or base that is not a multiple of 4, or a
+        // tile past the right edge): one byte per lane and row
+        gptr<T> row = (gptr<T>)im.J + (y0 + g) * im.ld + x0 + lane();
+        const int64_t rows_in = im.H - (y0 + g);
+#pragma unroll 1
+        for (int k = 0; k < NR; ++k) {
+          if (((rows >> k) & 1ull) && k < rows_in && col_in)
+            st_coherent(row, out(s.J[G::at(g + k, lane())], flip));
+          row += im.ld;
+        }
+        continue;
+      }
       // Every row's value is read from LDS before the first store: an LDS
       // read into a register that an outstanding store still reads would
       // make the store wait for completion (a store reads its registers
