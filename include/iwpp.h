@@ -39,7 +39,11 @@
  *    IWPP_FLAG_CLAMP_MARKER the marker is max(J, I).
  *  - The library keeps a workspace per (device, stream), grown on demand and
  *    freed by iwpp_release_workspace().  Calls on one stream run in stream
- *    order; calls on different streams may run concurrently.
+ *    order; calls on different streams may run concurrently.  Its largest
+ *    parts are per tile: a state word, a visited byte, an image index for
+ *    batches, and the tile's first and last column of I and J (so that a
+ *    neighbour reads them as one run): about 3% of the two images' bytes,
+ *    plus the tile queues.
  */
 #ifndef IWPP_H
 #define IWPP_H
