@@ -782,11 +782,21 @@ struct Tile {
                                      bool early) {
     int quiet = 0, k = 0;
     int res = kRoundsLeft;
+    // Each pass is idempotent: right after it, running it again changes
+    // nothing.  Bit p of `stale` is set while the tile or its halo may have
+    // changed since pass p last ran; a pass whose bit is clear is a no-op
+    // and counts as quiet without running (the pass that would confirm the
+    // fixed point at the end of a solve, most often).
+    uint32_t stale = 0xFu;
     for (; k < 4 * budget && quiet < 4; ++k) {
-      if (run_pass(s, (first_pass + k) & 3))
+      const int p = (first_pass + k) & 3;
+      if ((stale >> p & 1u) && run_pass(s, p)) {
         quiet = 0;
-      else
+        stale = 0xFu;
+      } else {
         ++quiet;
+      }
+      stale &= ~(1u << p);
       if (kStreaming && watch && (k & 3) == 3 && quiet < 4) {
         int amax;
         if (early && activation_mask(s, y0, x0, false, amax) != 0u) {
@@ -797,6 +807,7 @@ struct Tile {
         if (take_request(watch, peek_request(watch))) {
           refresh_halo(s, im, y0, x0, kp, t, tx, sides);
           quiet = 0;
+          stale = 0xFu;
         }
       }
     }
