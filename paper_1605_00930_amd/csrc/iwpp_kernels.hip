@@ -812,7 +812,9 @@ struct Tile {
       }
     }
     vs.rounds += (uint32_t)((k + 3) / 4);
-    return quiet >= 4 ? kFixed : res;
+    // with no pass stale, every pass has seen the tile as it is now: it is
+    // at its fixed point even if the budget ran out before four quiet passes
+    return (quiet >= 4 || stale == 0u) ? kFixed : res;
   }
 
   // ---------------------------------------------------------- seeds
