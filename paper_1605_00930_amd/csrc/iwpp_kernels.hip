@@ -487,21 +487,44 @@ struct Tile {
     return b;
   }
 
-  // One 8-connected step: returns min(ii, max(t0, p and the p of the lanes
-  // on either side)), and sets acc |= (p as it came in) ^ jprev, the change
-  // made by the step before (jprev is that step's old value; bitop3 0xbe is
-  // s2 | (s0 ^ s1)).  That bitop sits between the write of p and its DPP
-  // reads, which then come two wait states after it with no padding.
-  __device__ static int step8(int p, uint32_t& acc, int t0, int jprev, int ii) {
-    int b, r;
-    asm("v_max_i32 %1, %3, %4\n\t"
-        "v_bitop3_b32 %2, %3, %5, %2 bitop3:0xbe\n\t"
-        "v_max_i32_dpp %1, %3, %1 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-        "v_max_i32_dpp %1, %3, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-        "v_min_i32 %0, %1, %6"
-        : "=v"(r), "=&v"(b), "+v"(acc)
-        : "v"(p), "v"(t0), "v"(jprev), "v"(ii));
-    return r;
+  // Eight consecutive 8-connected steps of one chain in a single asm block.
+  // Step k sets r[k] = min(I, max(t[k], the chain value and the chain values
+  // of the lanes on either side)) and acc |= chain value ^ its old value,
+  // the change made by the step before (bitop3 0xbe is s2 | (s0 ^ s1)).
+  // The compiler cannot see into an asm block, so between two blocks it keeps
+  // a wait state for the DPP reads that might open the second: one block
+  // per step spends an s_nop per step, one block per eight steps one per
+  // eight.  In the block every DPP read of a chain value comes two wait
+  // states after its write (the max and the change bookkeeping sit
+  // between), as the hardware requires.
+  // On entry p is the chain value and jp the old value it replaced (equal
+  // to p for "no change"); t[k] is the value step k takes with the chain
+  // (its own J, for step 0 possibly raised by a halo corner) and o0 the old
+  // J of step 0 (the old J of steps 1..7 is t[k]); r[k] receives the results
+  // and acc the change bits of steps -1 .. 6 (the caller folds in step 7's).
+  __device__ static void step8x8(int p, uint32_t& acc, int jp, int o0, const int (&t)[8],
+                                 const int (&ii)[8], int (&r)[8]) {
+    int b;
+#define IWPP_V8(R, P, T, O, I)                                                  \
+  "v_max_i32 %8, " P ", " T "\n\t"                                             \
+  "v_bitop3_b32 %9, " P ", " O ", %9 bitop3:0xbe\n\t"                          \
+  "v_max_i32_dpp %8, " P ", %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"      \
+  "v_max_i32_dpp %8, " P ", %8 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"      \
+  "v_min_i32 " R ", %8, " I "\n\t"
+    asm(IWPP_V8("%0", "%10", "%13", "%11", "%21")
+        IWPP_V8("%1", "%0", "%14", "%12", "%22")
+        IWPP_V8("%2", "%1", "%15", "%14", "%23")
+        IWPP_V8("%3", "%2", "%16", "%15", "%24")
+        IWPP_V8("%4", "%3", "%17", "%16", "%25")
+        IWPP_V8("%5", "%4", "%18", "%17", "%26")
+        IWPP_V8("%6", "%5", "%19", "%18", "%27")
+        IWPP_V8("%7", "%6", "%20", "%19", "%28")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+          "=&v"(r[6]), "=&v"(r[7]), "=&v"(b), "+v"(acc)
+        : "v"(p), "v"(jp), "v"(o0), "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]), "v"(t[4]),
+          "v"(t[5]), "v"(t[6]), "v"(t[7]), "v"(ii[0]), "v"(ii[1]), "v"(ii[2]), "v"(ii[3]),
+          "v"(ii[4]), "v"(ii[5]), "v"(ii[6]), "v"(ii[7]));
+#undef IWPP_V8
   }
 
   // Down (D = +1) or up (D = -1) pass, one lane per column: each pixel takes
@@ -520,6 +543,35 @@ struct Tile {
   // next batch's rows are not written by the current one).
   static constexpr int B = 16;
   static_assert(TH % (2 * B) == 0, "the vertical pass works two batches per iteration");
+
+  // A batch of B steps of one 8-connected chain, eight steps per asm block.
+  // jj holds the own J of each step on entry and the results on return;
+  // `first` is the value step 0 takes with the chain in place of its own J
+  // (the own J raised by a halo corner).  The change bits of every step go
+  // to acc.
+  __device__ static void steps8(int& prev, uint32_t& acc, int first, int (&jj)[B],
+                                const int (&ii)[B]) {
+    static_assert(B % 8 == 0, "steps go eight to an asm block");
+    int jp = prev;  // the first step sees no change before it
+#pragma unroll
+    for (int g = 0; g < B; g += 8) {
+      int t[8], i8[8], r[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        t[k] = jj[g + k];
+        i8[k] = ii[g + k];
+      }
+      const int o0 = t[0];
+      if (g == 0) t[0] = first;
+      step8x8(prev, acc, jp, o0, t, i8, r);
+      jp = jj[g + 7];
+      prev = r[7];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) jj[g + k] = r[k];
+    }
+    acc |= (uint32_t)(prev ^ jp);
+  }
+
   template <int D>
   __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
@@ -538,15 +590,7 @@ struct Tile {
     auto work = [&](int kb, int (&jj)[B], const int (&ii)[B]) {
       uint32_t acc = 0;
       if constexpr (CONN == 8) {
-        int jprev = prev;  // the first step sees no change before it
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int old = jj[k];
-          prev = step8(prev, acc, k == 0 ? imax(old, corner) : old, jprev, ii[k]);
-          jprev = old;
-          jj[k] = prev;
-        }
-        acc |= (uint32_t)(prev ^ jprev);
+        steps8(prev, acc, imax(jj[0], corner), jj, ii);
       } else {
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -705,15 +749,7 @@ struct Tile {
           if (kFill) ff[k] = jv(s, fy, x);
         }
         if constexpr (CONN == 8 && !kFill) {
-          int jprev = prev;  // the first step sees no change before it
-#pragma unroll
-          for (int k = 0; k < B; ++k) {
-            const int old = jj[k];
-            prev = step8(prev, acc, old, jprev, ii[k]);
-            jprev = old;
-            jj[k] = prev;
-          }
-          acc |= (uint32_t)(prev ^ jprev);
+          steps8(prev, acc, jj[0], jj, ii);
         } else {
 #pragma unroll
           for (int k = 0; k < B; ++k) {
