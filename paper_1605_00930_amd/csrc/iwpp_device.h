@@ -194,14 +194,6 @@ __device__ __forceinline__ int* ring_slot(int* queue, const KParams& kp, int q, 
   return &queue[(int64_t)q * kp.qcap + (pos - len) % (int64_t)kp.qcap];
 }
 
-// Enqueue tile n (the caller has just moved it from idle to pending).
-static __device__ void queue_push(DevCtl* ctl, int* queue, const KParams& kp, int n) {
-  const int q = queue_of(kp, n);
-  const uint32_t pos = atomicAdd(&ctl->tail[q].v, 1u);
-  __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // No more work: tell every waiter.  Executed by a whole wavefront.
 static __device__ void stop_all(DevCtl* ctl, int* queue, const KParams& kp, int grid) {
   __hip_atomic_store(&ctl->done.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
