@@ -542,7 +542,7 @@ def main():
     if args.op != "dilate" and args.workload in ("c4", "c5", "edt", "edt32k"):
         ap.error("--op applies to single-image workloads only")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: runs on one GPU only (the multi-GPU split is a design, not code); --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
