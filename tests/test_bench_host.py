@@ -1,0 +1,70 @@
+"""Host logic of bench.py that needs no GPU: the counter-traffic summaries are
+used only for the kernel source they were taken on, the one-GPU limit is
+enforced before any device work, and the CPU baseline reports what it ran."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+WORKLOADS = ("c2", "c3i32", "c3u8")
+
+
+def summary_fields(workload):
+    path = os.path.join(bench.ROOT, "profiles", "traffic_k_persistent_%s.txt" % workload)
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+@pytest.mark.parametrize("workload", WORKLOADS)
+def test_traffic_used_only_for_its_kernel_source(workload, monkeypatch):
+    kv = summary_fields(workload)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: kv["kernel_source_sha256"])
+    assert bench.load_traffic(workload) == float(kv["traffic_bytes_per_launch"])
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.load_traffic(workload) is None
+
+
+@pytest.mark.parametrize("workload", WORKLOADS)
+def test_traffic_summary_is_consistent(workload):
+    kv = summary_fields(workload)
+    fetch = float(kv["fetch_bytes_per_launch"])
+    write = float(kv["write_bytes_per_launch"])
+    algo = float(kv["algorithmic_bytes_per_launch"])
+    assert float(kv["traffic_bytes_per_launch"]) == pytest.approx(fetch + write, rel=1e-9, abs=1)
+    assert float(kv["traffic_over_algorithmic"]) == pytest.approx((fetch + write) / algo,
+                                                                  abs=1e-3)
+    # the workload's algorithmic bytes: read I and J, write R, sizeof(T) each
+    side = 4096 if workload == "c2" else 32768
+    per_px = 12 if workload == "c3i32" else 3
+    assert algo == per_px * side * side
+    # every dispatch listed contributes; the calibration scale turns KiB into bytes
+    kib = [float(x) for x in kv["k_persistent_fetch_kib_per_dispatch"].split(",")]
+    assert min(kib) > 0
+
+
+def test_traffic_missing_summary_is_none():
+    assert bench.load_traffic("no_such_workload") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_cpu_baseline_reports_its_sample():
+    cb = bench.cpu_baseline("c1", budget_s=0.05)
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "Mpixel/s"
+    assert cb["value"] > 0
+    assert cb["sample"].startswith("full 512x512 image")
