@@ -1,5 +1,6 @@
-"""Parity at the full 32768 x 32768 sizes, in the configuration bench.py
-times (library defaults, 8-connected).
+"""Parity at the full sizes, in the configurations bench.py times
+(8-connected; library defaults for single images, tuned parameters and a
+HIP-graph plan for the 256-image batch).
 
 * int32 h-dome: the whole image is compared with the oracle, bit for bit
   (the oracle takes about 35 s of one core).
@@ -10,6 +11,8 @@ times (library defaults, 8-connected).
   - R at sampled pixels, computed one by one by the oracle's single-pixel
     search (samples whose search exceeds its visit bound are skipped; most
     samples near the frame complete).
+* the 256-image batch (about 1 Gpx): J <= R <= I for every image after each
+  graph replay, and 16 sampled images against the oracle, bit for bit.
 """
 from __future__ import annotations
 
@@ -111,3 +114,50 @@ def test_c3_u8_full_size_properties_and_samples(iwpp):
     announce("c3 uint8: %d of %d samples completed" % (done.sum(), done.size))
     assert done.sum() >= 250
     np.testing.assert_array_equal(R[rows[done], cols[done]].astype(np.int32), vals[done])
+
+
+def test_c4_full_batch_sampled(iwpp):
+    """The 256-image batch at its full sizes (sides log-uniform 512..4096,
+    about 1 Gpx), run as bench.py runs it: parameters tuned on the largest
+    image, one plan, launched as a HIP graph and replayed.  Every image is
+    checked for J <= R <= I after each replay; 16 images (the smallest, the
+    largest and 14 drawn at random) are compared with the oracle bit for bit,
+    after the second replay."""
+    import torch
+
+    announce("c4 256 images: generating")
+    pairs = synth.c4()
+    dev = torch.device("cuda:0")
+    pristine = [torch.from_numpy(J).to(dev) for I, J in pairs]
+    masks = [torch.from_numpy(I).to(dev) for I, J in pairs]
+    work = [p.clone() for p in pristine]
+    big = max(range(len(masks)), key=lambda k: masks[k].numel())
+    announce("c4 256 images: tuning on image %d" % big)
+    tuned = {k: v for k, v in iwpp.autotune(pristine[big], masks[big], 8).items() if v}
+    plan = iwpp.Batch(list(zip(work, masks)), 8, params=tuned)
+    try:
+        for replay in range(2):
+            for w, p in zip(work, pristine):
+                w.copy_(p)
+            announce("c4 256 images: graph launch %d, params %s" % (replay, tuned))
+            plan.launch(graph=True)
+            st = plan.status()
+            assert st["rc"] == iwpp.OK and st["images"] == 256
+            for k, (w, p, m) in enumerate(zip(work, pristine, masks)):
+                assert bool((w >= p).all()) and bool((w <= m).all()), "image %d" % k
+    finally:
+        plan.close()
+    rng = np.random.default_rng(5)
+    small = min(range(len(masks)), key=lambda k: masks[k].numel())
+    picks = sorted({small, big} | set(int(k) for k in rng.choice(len(pairs), 14, replace=False)))
+    for k in picks:
+        I, J = pairs[k]
+        announce("c4 image %d (%dx%d): oracle" % (k, I.shape[0], I.shape[1]))
+        rc, R = oracle.reconstruct(J, I, 8)
+        assert rc == oracle.OK
+        got = work[k].cpu().numpy()
+        bad = got != R
+        if bad.any():
+            y, x = np.argwhere(bad)[0]
+            raise AssertionError("image %d: %d pixels differ, first at (%d, %d): got %d want %d"
+                                 % (k, bad.sum(), y, x, got[y, x], R[y, x]))
