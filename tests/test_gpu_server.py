@@ -110,3 +110,36 @@ def test_server_wait_timeout_and_unknown_ticket(iwpp):
     assert rc == iwpp.E_ARG
     srv.close()
     np.testing.assert_array_equal(o.cpu().numpy(), _expect(I, J))
+
+
+def test_server_full_size_stream(iwpp):
+    """Requests at the served stream's full sizes (sides log-uniform
+    256..8192, h-dome and fill-holes markers), three copies of each in a
+    shuffled order, through a server set up as the benchmark sets it up
+    (64 GB budget, two launch slots, up to 64 in flight): every result equals
+    the oracle's for its request."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    pool = synth.c5_pool(seed=11, n=12, lo=256, hi=8192)
+    print("[gpu-case] server full-size stream: %s"
+          % [(I.shape[0], kind) for I, _, kind in pool], flush=True)
+    masks = [torch.from_numpy(I).to(dev) for I, J, _ in pool]
+    pristine = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
+    order = np.random.default_rng(12).permutation(np.repeat(np.arange(len(pool)), 3))
+    srv = iwpp.Server(64 << 30, "u8", 8, streams=2, max_inflight=64)
+    try:
+        outs = []
+        for k in order:
+            out = torch.empty_like(pristine[k])
+            outs.append((int(k), out, srv.submit(out, masks[k], marker_init=pristine[k])))
+        for k, _, t in outs:
+            rc, lat = srv.wait(t)
+            assert rc == iwpp.OK and lat > 0
+    finally:
+        srv.close()
+    for k, (I, J, _) in enumerate(pool):
+        want = _expect(I, J)
+        for kk, out, _ in outs:
+            if kk == k:
+                np.testing.assert_array_equal(out.cpu().numpy(), want)
