@@ -8,10 +8,11 @@ from a pristine device copy; that copy is not part of the step's timed
 region (hipEvents around the library call on the bench's stream).
 
 Workloads (--workload):
-  c2     4096x4096 uint8 tissue-like ellipses, fill-holes marker (default)
+  c3i32  32768x32768 int32 smooth field, h-dome marker I - 4096 (default: the
+         largest single-image configuration, in the paper's 32-bit integers)
   c1     512x512 uint8 Gaussian blobs, h-dome marker (latency bound)
+  c2     4096x4096 uint8 tissue-like ellipses, fill-holes marker
   c3u8   32768x32768 uint8 ellipses, fill-holes marker
-  c3i32  32768x32768 int32 smooth field, h-dome marker I - 4096
   c4     256 images, sides log-uniform 512..4096, one batched launch
          (HIP graph) vs the per-image loop
   c5     served stream: Poisson arrivals at 2000 req/s into the
@@ -39,8 +40,18 @@ Extras in the JSON line:
                 hipEvent-measured duration, against 8 TB/s; `traffic` from the
                 committed rocprofv3 counter summary when it matches the
                 current kernel source, else null.
-  cpu_baseline  the CPU oracle (sequential C) timed on this host on a bounded
-                sample of the same workload.
+  parity        sha256 of the inputs and of the last timed output against the
+                digests of the CPU oracle's result stored in
+                tests/golden/full_size_sha256.txt (bit-exact check of the
+                timed work itself).
+  cv_protocol   the paper's timing protocol (10 runs, coefficient of variation
+                at most 1%): whether the timed steps met it.
+  also          (single-image default) the 4096^2 and 32768^2 uint8
+                fill-holes workloads, timed the same way with fewer steps.
+  cpu_baseline  the CPU oracle (sequential C) timed on this host: one core on
+                the whole image for single images (the paper's serial
+                baseline), all host cores (a process pool, one image or
+                request per task) for the batch and the served stream.
 """
 from __future__ import annotations
 
@@ -93,6 +104,31 @@ def load_traffic(workload: str):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size_sha256.txt")
+
+
+def golden():
+    """name -> (sha256 I, sha256 J, sha256 R) of the oracle's result, from the
+    digests written by tests/golden/make_full_size_hashes.py."""
+    out = {}
+    if os.path.exists(GOLDEN):
+        for ln in open(GOLDEN):
+            if ln.startswith("#") or not ln.strip():
+                continue
+            f = ln.split()
+            out[f[0]] = (f[4], f[5], f[6])
+    return out
+
+
+def host_cores() -> int:
+    """Host threads for the pooled CPU baselines: the box's share for one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def make_workload(name: str, scale: int = 1):
@@ -176,31 +212,62 @@ def bench_edt(args, torch, iwpp):
     }
 
 
-def cpu_baseline(name: str, budget_s: float = 20.0, op: str = "dilate"):
-    """Time the oracle (single thread) on a bounded sample of the workload."""
+def _oracle_task(spec):
+    """One pooled oracle run (a child process): reconstruct image or request
+    ``k`` of the batch / pool recipe and return (pixels, seconds)."""
     import oracle
     import synth
 
-    if name == "c1":
-        pairs = [synth.c1()]
-        sample = "full 512x512 image"
-    elif name == "c2":
-        pairs = [synth.c2()]
-        sample = "full 4096x4096 image"
-    elif name == "c3u8":
-        pairs = [synth.c3_u8(H=8192, W=8192)]
-        sample = "8192x8192 image of the same recipe (ellipse count scaled by area)"
-    elif name == "c3i32":
-        pairs = [synth.c3_i32(H=8192, W=8192)]
-        sample = "8192x8192 image of the same recipe"
-    elif name in ("c4", "c5"):
-        pairs = synth.c4(n=24)
-        sample = "first 24 images of the batch recipe"
-    elif name in ("edt", "edt32k"):
+    kind, k = spec
+    if kind == "c4":
+        (I, J), = synth.c4(only=[k])
+    else:
+        (I, J, _), = synth.c5_pool(n=256, only=[k])
+    t0 = time.perf_counter()
+    rc, _ = oracle.reconstruct(J, I, 8)
+    dt = time.perf_counter() - t0
+    assert rc == oracle.OK
+    return I.size, dt
+
+
+def cpu_baseline(name: str, budget_s: float = 0.0, op: str = "dilate", pool: int = 256):
+    """Time the oracle on this host.
+
+    Single images: one core on the whole image (the paper's serial baseline),
+    repeated while within ``budget_s`` (at least once, at most 10 runs).
+    Batch and served stream: a process pool over all host cores (at most the
+    16 of one GPU's share), one image or request per task, over the whole
+    batch or pool; the rate is pixels (or requests) over the pool's wall time.
+    ``budget_s`` > 0 bounds the 32768^2 images to their first run."""
+    import oracle
+    import synth
+
+    if name in ("c4", "c5"):
+        from concurrent.futures import ProcessPoolExecutor
+
+        n = 256 if name == "c4" else pool
+        cores = host_cores()
+        specs = [(name, k) for k in range(n)]
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=cores) as ex:
+            res = list(ex.map(_oracle_task, specs, chunksize=1))
+        wall = time.perf_counter() - t0
+        px = sum(r[0] for r in res)
+        busy = sum(r[1] for r in res)
+        out = {"value": round(px / wall / 1e6, 3), "unit": "Mpixel/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "all %d %s on a pool of %d processes (generation included in the "
+                         "wall time, %.1f s of it reconstructing)" % (
+                             n, "images of the batch" if name == "c4" else
+                             "requests of the pool", cores, busy)}
+        if name == "c5":
+            out["req_s"] = round(n / wall, 2)
+        return out
+    if name in ("edt", "edt32k"):
         img = edt_image("edt")
         px = t = 0.0
         runs = 0
-        while t < budget_s and runs < 10:
+        while runs < 1 or (t < max(budget_s, 10.0) and runs < 10):
             t0 = time.perf_counter()
             rc, _, _ = oracle.edt(img, 8)
             t += time.perf_counter() - t0
@@ -210,39 +277,61 @@ def cpu_baseline(name: str, budget_s: float = 20.0, op: str = "dilate"):
         return {"value": round(px / t / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
                 "kind": "oracle", "sample": "4096x4096 image of the edt recipe, %d run(s), "
                                             "%.1f s of CPU time" % (runs, t)}
+    if name == "c1":
+        I, J = synth.c1()
+    elif name == "c2":
+        I, J = synth.c2()
+    elif name == "c3u8":
+        I, J = synth.c3_u8()
+    elif name == "c3i32":
+        I, J = synth.c3_i32()
     else:
         raise ValueError(name)
-    px = 0
-    t = 0.0
-    runs = 0
-    while t < budget_s and runs < 10:
-        for I, J in pairs:
-            if op == "erode":
-                J, I = np.invert(J), np.invert(I)
-            t0 = time.perf_counter()
-            if op == "fill":
-                rc, _ = oracle.fill_holes(I, 8)
-            elif op == "erode":
-                rc, _ = oracle.reconstruct_erode(J, I, 8)
-            else:
-                rc, _ = oracle.reconstruct(J, I, 8)
-            t += time.perf_counter() - t0
-            assert rc == 0
-            px += I.size
-        runs += 1
-    return {"value": round(px / t / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-            "sample": "%s, %d run(s), %.1f s of CPU time" % (sample, runs, t)}
+    if op == "erode":
+        J, I = np.invert(J), np.invert(I)
+    big = I.size > 1 << 26
+    limit = budget_s if budget_s > 0 else (0.0 if big else 20.0)
+    times = []
+    while not times or (sum(times) < limit and len(times) < 10):
+        t0 = time.perf_counter()
+        if op == "fill":
+            rc, _ = oracle.fill_holes(I, 8)
+        elif op == "erode":
+            rc, _ = oracle.reconstruct_erode(J, I, 8)
+        else:
+            rc, _ = oracle.reconstruct(J, I, 8)
+        times.append(time.perf_counter() - t0)
+        assert rc == 0
+    t = float(np.median(times))
+    return {"value": round(I.size / t / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "whole %dx%d image, median of %d run(s) on one core, %.1f s of CPU time"
+                      % (I.shape[0], I.shape[1], len(times), sum(times))}
 
 
-def bench_single(args, torch, iwpp):
+def cv_protocol(times):
+    """The paper's protocol: 10 runs per configuration with a coefficient of
+    variation of at most 1%."""
+    cv = float(np.std(times) / np.mean(times))
+    return {"runs": len(times), "cv": round(cv, 4), "bound": 0.01,
+            "held": bool(len(times) >= 10 and cv <= 0.01)}
+
+
+def bench_single(args, torch, iwpp, workload=None, steps=None, warmup=None, quiet=False):
+    workload = workload or args.workload
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    pairs, dt, desc = make_workload(args.workload, args.scale)
-    log("generated %s in %.1f s" % (args.workload, time.perf_counter() - t0))
+    pairs, dt, desc = make_workload(workload, args.scale)
+    log("generated %s in %.1f s" % (workload, time.perf_counter() - t0))
     (I, J), = pairs
     if args.op == "erode":
         I, J = np.invert(I), np.invert(J)
     H, W = I.shape
+    import synth
+
+    in_sha = {"I": synth.sha256(I), "J": synth.sha256(J)}
     Jt0 = torch.from_numpy(J).to(dev)
     It = torch.from_numpy(I).to(dev)
     del pairs, I, J
@@ -264,8 +353,8 @@ def bench_single(args, torch, iwpp):
     ev1 = torch.cuda.Event(enable_timing=True)
     call_ms, kern_ms, stats = [], [], None
     torch.cuda.synchronize()
-    for step in range(args.warmup + args.steps):
-        if step == args.warmup:
+    for step in range(warmup + steps):
+        if step == warmup:
             torch.cuda.synchronize()
             t_wall0 = time.perf_counter()
         with torch.cuda.stream(stream):
@@ -280,26 +369,41 @@ def bench_single(args, torch, iwpp):
                                        erosion=args.op == "erode")
                 ev1.record(stream)
         st = iwpp.stream_status(stream)
-        log("step %d: %.3f ms (kernel %.3f ms, visits %d)"
-            % (step, ev0.elapsed_time(ev1), st["kernel_ms"], st["tile_visits"]))
-        if step >= args.warmup:
+        if not quiet or step == warmup + steps - 1:
+            log("%s step %d: %.3f ms (kernel %.3f ms, visits %d)"
+                % (workload, step, ev0.elapsed_time(ev1), st["kernel_ms"], st["tile_visits"]))
+        if st["rc"] != iwpp.OK:
+            raise RuntimeError("%s step %d: status %d" % (workload, step, st["rc"]))
+        if step >= warmup:
             call_ms.append(ev0.elapsed_time(ev1))
             kern_ms.append(st["kernel_ms"])
             stats = st
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall0
+    # bit-exactness of the last timed output: its digest against the oracle's
+    out_sha = synth.sha256(Jt.cpu().numpy())
+    want = golden().get(workload) if (args.op == "dilate" and args.scale == 1) else None
+    if want is None:
+        parity = {"checked": False, "reason": "no stored oracle digest for this workload/op/scale",
+                  "inputs_sha256": in_sha, "output_sha256": out_sha}
+    else:
+        parity = {"checked": True, "inputs_match": in_sha["I"] == want[0] and in_sha["J"] == want[1],
+                  "bit_exact": out_sha == want[2], "inputs_sha256": in_sha,
+                  "output_sha256": out_sha, "oracle_sha256": want[2]}
+    del Jt, Jt0, It
+    torch.cuda.empty_cache()
     es = 1 if dt == "u8" else 4
     ms = float(np.mean(call_ms))
     kms = float(np.mean(kern_ms))
     px = H * W
     achieved = 3 * es * px / (kms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload) if args.op == "dilate" else None
+    traffic = load_traffic(workload) if args.op == "dilate" else None
     res = {
         "metric": METRIC, "value": round(px / (ms * 1e-3) / 1e6, 2), "unit": "Mpixel/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic",
-        "config": {"workload": args.workload, "op": args.op, "desc": desc, "H": H, "W": W,
+        "config": {"workload": workload, "op": args.op, "desc": desc, "H": H, "W": W,
                    "conn": 8, "autotuned": tuned is not None,
                    "params": {k: v for k, v in params.items() if k != "timing"}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -307,19 +411,27 @@ def bench_single(args, torch, iwpp):
                      "traffic": traffic,
                      "kernel": "k_persistent (tile worker)", "kernel_ms": round(kms, 4),
                      "algorithmic_bytes_per_launch": 3 * es * px},
+        "parity": parity,
         "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
                                              "pixels_queued", "queue_overflows", "reprocessed",
                                              "queue_iterations", "idle_ms", "load_ms", "solve_ms",
                                              "store_ms", "sync_ms")},
         "ms_min": round(float(np.min(call_ms)), 4), "ms_cv": round(float(np.std(call_ms) / ms), 4),
-        "wall_ms_per_step_incl_restore": round(wall * 1e3 / args.steps, 4),
+        "cv_protocol": cv_protocol(call_ms),
+        "wall_ms_per_step_incl_restore": round(wall * 1e3 / steps, 4),
     }
     return res
 
 
 def bench_batched(args, torch, iwpp):
     dev = torch.device("cuda:0")
+    import synth
+
     pairs, dt, desc = make_workload("c4")
+    want = golden()
+    inputs_match = all(synth.sha256(I) == want.get("c4/%d" % k, ("",) * 3)[0]
+                       and synth.sha256(J) == want.get("c4/%d" % k, ("",) * 3)[1]
+                       for k, (I, J) in enumerate(pairs))
     pristine = [torch.from_numpy(J).to(dev) for I, J in pairs]
     masks = [torch.from_numpy(I).to(dev) for I, J in pairs]
     px = sum(I.size for I, J in pairs)
@@ -365,6 +477,11 @@ def bench_batched(args, torch, iwpp):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall0
     plan.close()
+    # bit-exactness of the last timed launch: every image's digest against the oracle's
+    differ = [k for k, w in enumerate(work)
+              if synth.sha256(w.cpu().numpy()) != want.get("c4/%d" % k, ("",) * 3)[2]]
+    parity = {"checked": len(want) > 0, "images": len(work), "inputs_match": inputs_match,
+              "bit_exact": not differ, "images_differing": differ[:16]}
     # the plain per-image path on the same GPU, for comparison
     per_image = []
     lat = []
@@ -411,6 +528,8 @@ def bench_batched(args, torch, iwpp):
                            "image_ms_p50": round(lats[len(lats) // 2], 4),
                            "image_ms_p99": round(lats[min(len(lats) - 1, int(0.99 * len(lats)))], 4)},
         "batched_speedup_vs_loop": round(per_image[0] / ms, 3),
+        "parity": parity,
+        "cv_protocol": cv_protocol(times),
         "wall_ms_per_step_incl_restore": round(wall * 1e3 / args.steps, 4),
     }
 
@@ -489,6 +608,18 @@ def bench_served(args, torch, iwpp):
     th.join()
     wall = time.perf_counter() - start
     srv.close()
+    # bit-exactness: the last result held by working marker 0 of every pool
+    # request that ran, against the oracle's digest (the pool of 256 requests
+    # drawn with seed 4 is the one the digests cover)
+    want = golden()
+    used = [k for k in range(len(masks)) if uses[k] > 0]
+    if len(masks) == 256:
+        differ = [k for k in used
+                  if synth.sha256(work[k][0].cpu().numpy()) != want.get("c5/%d" % k, ("",) * 3)[2]]
+        parity = {"checked": True, "requests_checked": len(used), "bit_exact": not differ,
+                  "requests_differing": differ[:16]}
+    else:
+        parity = {"checked": False, "reason": "digests cover the 256-request pool only"}
     lat_ms = sorted(x / 1e3 for x in lat)
     value = done_px[0] / wall / 1e6
     return {
@@ -505,6 +636,7 @@ def bench_served(args, torch, iwpp):
                    "p50_ms": round(lat_ms[len(lat_ms) // 2], 3),
                    "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 3),
                    "max_ms": round(lat_ms[-1], 3), "wall_s": round(wall, 3)},
+        "parity": parity,
     }
 
 
@@ -513,7 +645,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2",
+    ap.add_argument("--workload", default="c3i32",
                     choices=["c1", "c2", "c3u8", "c3i32", "c4", "c5", "edt", "edt32k"])
     ap.add_argument("--scale", type=int, default=1, help="divide the 32K side (c3*) by this")
     ap.add_argument("--op", default="dilate", choices=["dilate", "erode", "fill"],
@@ -529,13 +661,20 @@ def main():
                     help="tune parameters on the resident workload before timing, outside the "
                          "timed region (auto: on for c4 only, whose recipe asks for it)")
     ap.add_argument("--rate", type=float, default=2000.0, help="c5 arrivals per second")
-    ap.add_argument("--duration", type=float, default=3.0, help="c5 seconds of arrivals")
-    ap.add_argument("--pool", type=int, default=64, help="c5 distinct requests")
-    ap.add_argument("--copies", type=int, default=32, help="c5 working markers per pool request")
+    ap.add_argument("--duration", type=float, default=10.0, help="c5 seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=256, help="c5 distinct requests")
+    ap.add_argument("--copies", type=int, default=4, help="c5 working markers per pool request")
     ap.add_argument("--streams", type=int, default=2, help="c5 server launch slots")
     ap.add_argument("--max-inflight", dest="max_inflight", type=int, default=64)
     ap.add_argument("--budget-gb", dest="budget_gb", type=float, default=64.0)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=0.0,
+                    help="seconds of oracle runs for single images (0: one run of a 32768^2 "
+                         "image, up to 20 s of runs otherwise)")
+    ap.add_argument("--also", default="auto",
+                    help="comma-separated single-image workloads timed after the main one and "
+                         "reported under 'also' (auto: c2,c3u8 when the main workload is the "
+                         "default c3i32 dilation; none: skip)")
+    ap.add_argument("--also-steps", dest="also_steps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run the library copy kernel on this many MiB (profiler scaling)")
     args = ap.parse_args()
@@ -577,8 +716,20 @@ def main():
         res = bench_edt(args, torch, iwpp)
     else:
         res = bench_single(args, torch, iwpp)
+        also = args.also
+        if also == "auto":
+            also = "c2,c3u8" if (args.workload == "c3i32" and args.op == "dilate"
+                                 and args.scale == 1 and args.mode is None) else "none"
+        if also != "none":
+            res["also"] = {}
+            for w in also.split(","):
+                r = bench_single(args, torch, iwpp, workload=w, steps=args.also_steps,
+                                 warmup=3, quiet=True)
+                res["also"][w] = {k: r[k] for k in ("value", "unit", "ms_per_step", "dtype",
+                                                    "config", "roofline", "parity",
+                                                    "cv_protocol", "step_stats")}
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.op)
+        res["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_budget, args.op, args.pool)
     res["kernel_source_sha256"] = kernel_source_hash()
     print(json.dumps(res), flush=True)
 

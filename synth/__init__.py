@@ -176,15 +176,16 @@ def log_uniform_sides(rng: np.random.Generator, n: int, lo: int, hi: int) -> np.
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), n))).astype(np.int64)
 
 
-def c4(seed: int = 3, n: int = 256, lo: int = 512, hi: int = 4096):
+def c4(seed: int = 3, n: int = 256, lo: int = 512, hi: int = 4096, only=None):
     """n square uint8 images, sides log-uniform in [lo, hi], ellipse masks
     (3000 ellipses per 4096^2, scaled by area), h-dome markers with
-    h ~ U{10..80}.  Returns a list of (I, J)."""
+    h ~ U{10..80}.  Returns a list of (I, J); with ``only`` (indices), just
+    those images, drawn exactly as in the whole batch."""
     rng = np.random.default_rng(seed)
     sides = log_uniform_sides(rng, n, lo, hi)
     hs = rng.integers(10, 81, size=n)
     out = []
-    for i in range(n):
+    for i in range(n) if only is None else only:
         s = int(sides[i])
         ne = max(1, round(3000 * s * s / (4096 * 4096)))
         I = ellipses(np.random.default_rng([seed, i]), s, s, ne)
@@ -192,16 +193,17 @@ def c4(seed: int = 3, n: int = 256, lo: int = 512, hi: int = 4096):
     return out
 
 
-def c5_pool(seed: int = 4, n: int = 64, lo: int = 256, hi: int = 8192):
+def c5_pool(seed: int = 4, n: int = 256, lo: int = 256, hi: int = 8192, only=None):
     """A pool of n distinct uint8 requests: sides log-uniform in [lo, hi],
     ellipse masks, markers half h-dome (h ~ U{10..80}) and half fill-holes
-    frame.  Returns a list of (I, J, kind)."""
+    frame.  Returns a list of (I, J, kind); with ``only`` (indices), just
+    those requests, drawn exactly as in the whole pool."""
     rng = np.random.default_rng(seed)
     sides = log_uniform_sides(rng, n, lo, hi)
     kinds = rng.integers(0, 2, size=n)
     hs = rng.integers(10, 81, size=n)
     out = []
-    for i in range(n):
+    for i in range(n) if only is None else only:
         s = int(sides[i])
         ne = max(1, round(3000 * s * s / (4096 * 4096)))
         I = ellipses(np.random.default_rng([seed, 1000 + i]), s, s, ne)

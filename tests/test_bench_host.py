@@ -67,4 +67,29 @@ def test_cpu_baseline_reports_its_sample():
     cb = bench.cpu_baseline("c1", budget_s=0.05)
     assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "Mpixel/s"
     assert cb["value"] > 0
-    assert cb["sample"].startswith("full 512x512 image")
+    assert cb["sample"].startswith("whole 512x512 image")
+
+
+def test_pooled_oracle_task_matches_the_batch_recipe():
+    # one task of the all-core batch baseline reconstructs image k of the
+    # whole batch recipe
+    import synth
+
+    px, dt = bench._oracle_task(("c4", 3))
+    (I, _), = synth.c4(only=[3])
+    assert px == I.size and dt > 0
+    assert synth.sha256(*synth.c4(only=[3])[0]) == synth.sha256(*synth.c4()[3])
+
+
+def test_cv_protocol():
+    assert bench.cv_protocol([1.0] * 10) == {"runs": 10, "cv": 0.0, "bound": 0.01, "held": True}
+    assert not bench.cv_protocol([1.0] * 9)["held"]
+    assert not bench.cv_protocol([1.0, 1.1] * 5)["held"]
+
+
+def test_golden_digests_cover_every_workload():
+    g = bench.golden()
+    for name in ("c1", "c2", "c3i32", "c3u8"):
+        assert name in g
+    assert all("c4/%d" % k in g for k in range(256))
+    assert all("c5/%d" % k in g for k in range(256))

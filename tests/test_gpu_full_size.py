@@ -2,20 +2,21 @@
 (8-connected; library defaults for single images, tuned parameters and a
 HIP-graph plan for the 256-image batch).
 
-* int32 h-dome: the whole image is compared with the oracle, bit for bit
-  (the oracle takes about 35 s of one core).
-* uint8 fill-holes: the oracle would take minutes, so the check is
-  - properties that hold at any size, computed with plain torch tensor ops:
-    J <= R <= I, the fixed-point equation R = min(I, max(R, its 8
-    neighbours)) at every pixel, and max R <= max J;
-  - R at sampled pixels, computed one by one by the oracle's single-pixel
-    search (samples whose search exceeds its visit bound are skipped; most
-    samples near the frame complete).
-* the 256-image batch (about 1 Gpx): J <= R <= I for every image after each
-  graph replay, and 16 sampled images against the oracle, bit for bit.
+Every image is compared whole: the sha256 of the library's output must equal
+the sha256 of the CPU oracle's reconstruction of the same inputs, stored in
+tests/golden/full_size_sha256.txt by tests/golden/make_full_size_hashes.py
+(which calls only the oracle and the seeded generators).  The inputs' own
+digests are checked first, so a drift of the generators cannot pass as a
+parity failure or hide one.
+
+On a mismatch the tests locate the difference for the report (diagnostics
+only, never the pass criterion): the int32 image against the oracle run on
+the spot, the uint8 image through properties and sampled single-pixel oracle
+searches, a batch image against the oracle.
 """
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -25,6 +26,22 @@ import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "full_size_sha256.txt")
+
+
+def golden():
+    """name -> {"I", "J", "R"} sha256 digests (and shape, dtype, conn)."""
+    out = {}
+    with open(GOLDEN) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            name, shape, dt, conn, hI, hJ, hR = ln.split()
+            out[name] = {"shape": shape, "dtype": dt, "conn": int(conn),
+                         "I": hI, "J": hJ, "R": hR}
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -44,11 +61,25 @@ def announce(msg):
     sys.stdout.flush()
 
 
+def _check_inputs(g, name, I, J):
+    assert synth.sha256(I) == g[name]["I"], "%s: mask differs from the stored inputs" % name
+    assert synth.sha256(J) == g[name]["J"], "%s: marker differs from the stored inputs" % name
+
+
+def _first_difference(got, want):
+    bad = got != want
+    y, x = np.argwhere(bad)[0]
+    return "%d pixels differ, first at (%d, %d): got %d want %d" % (
+        bad.sum(), y, x, got[y, x], want[y, x])
+
+
 def test_c3_i32_full_size_bit_exact(iwpp):
     import torch
 
+    g = golden()
     announce("c3 int32 32768x32768: generating")
     I, J = synth.c3_i32()
+    _check_inputs(g, "c3i32", I, J)
     dev = torch.device("cuda:0")
     announce("c3 int32 32768x32768: GPU reconstruction")
     Jt = torch.from_numpy(J).to(dev)
@@ -58,21 +89,22 @@ def test_c3_i32_full_size_bit_exact(iwpp):
     got = Jt.cpu().numpy()
     del Jt, It
     torch.cuda.empty_cache()
-    announce("c3 int32 32768x32768: oracle (about 35 s)")
+    announce("c3 int32: hashing the whole output")
+    if synth.sha256(got) == g["c3i32"]["R"]:
+        return
+    announce("c3 int32: digest differs; oracle for the report (about 35 s)")
     rc, _ = oracle.reconstruct(J, I, 8, inplace=True)
     assert rc == oracle.OK
-    bad = got != J
-    if bad.any():
-        y, x = np.argwhere(bad)[0]
-        raise AssertionError("%d pixels differ, first at (%d, %d): got %d want %d"
-                             % (bad.sum(), y, x, got[y, x], J[y, x]))
+    raise AssertionError("c3 int32: " + _first_difference(got, J))
 
 
-def test_c3_u8_full_size_properties_and_samples(iwpp):
+def test_c3_u8_full_size_bit_exact(iwpp):
     import torch
 
+    g = golden()
     announce("c3 uint8 32768x32768: generating")
     I, J = synth.c3_u8()
+    _check_inputs(g, "c3u8", I, J)
     H, W = I.shape
     dev = torch.device("cuda:0")
     announce("c3 uint8 32768x32768: GPU reconstruction")
@@ -80,11 +112,15 @@ def test_c3_u8_full_size_properties_and_samples(iwpp):
     It = torch.from_numpy(I).to(dev)
     Rt = Jt.clone()
     iwpp.reconstruct(Rt, It, 8)
-    announce("c3 uint8: properties")
-    assert bool((Jt <= Rt).all()) and bool((Rt <= It).all())
-    assert int(Rt.max()) <= int(Jt.max())
-    # fixed point: R = min(I, max over the pixel and its 8 neighbours of R);
-    # pixels outside the image take no part (padding with 0, the uint8 floor)
+    R = Rt.cpu().numpy()
+    announce("c3 uint8: hashing the whole output")
+    if synth.sha256(R) == g["c3u8"]["R"]:
+        return
+    # diagnostics: which property fails, and sampled pixels against the
+    # oracle's single-pixel search
+    msgs = []
+    if not (bool((Jt <= Rt).all()) and bool((Rt <= It).all())):
+        msgs.append("J <= R <= I fails")
     P = torch.zeros((H + 2, W + 2), dtype=torch.uint8, device=dev)
     P[1:-1, 1:-1] = Rt
     m = Rt.clone()
@@ -93,40 +129,33 @@ def test_c3_u8_full_size_properties_and_samples(iwpp):
             if dy or dx:
                 torch.maximum(m, P[1 + dy:1 + dy + H, 1 + dx:1 + dx + W], out=m)
     del P
-    assert torch.equal(Rt, torch.minimum(It, m))
-    del m
-    R = Rt.cpu().numpy()
-    del Rt, Jt, It
+    if not torch.equal(Rt, torch.minimum(It, m)):
+        msgs.append("not a fixed point")
+    del m, Rt, Jt, It
     torch.cuda.empty_cache()
-    announce("c3 uint8: sampled pixels")
     rng = np.random.default_rng(77)
-    n_edge, n_any = 300, 60
-    side = rng.integers(0, 4, n_edge)
-    depth = rng.integers(0, 300, n_edge)
-    along = rng.integers(0, W, n_edge)
-    rows = np.where(side == 0, depth, np.where(side == 1, H - 1 - depth, along % H))
-    cols = np.where(side == 2, depth, np.where(side == 3, W - 1 - depth, along))
-    rows = np.concatenate([rows, rng.integers(0, H, n_any)])
-    cols = np.concatenate([cols, rng.integers(0, W, n_any)])
+    rows = rng.integers(0, H, 200)
+    cols = rng.integers(0, W, 200)
     rc, vals = oracle.pixels(J, I, rows, cols, 8, max_visit=1_500_000)
-    assert rc in (oracle.OK, oracle.E_INCOMPLETE)
     done = vals != np.iinfo(np.int32).min
-    announce("c3 uint8: %d of %d samples completed" % (done.sum(), done.size))
-    assert done.sum() >= 250
-    np.testing.assert_array_equal(R[rows[done], cols[done]].astype(np.int32), vals[done])
+    wrong = done & (R[rows, cols].astype(np.int32) != vals)
+    msgs.append("%d of %d completed samples differ" % (wrong.sum(), done.sum()))
+    raise AssertionError("c3 uint8: digest differs from the oracle's; " + "; ".join(msgs))
 
 
-def test_c4_full_batch_sampled(iwpp):
+def test_c4_full_batch_bit_exact(iwpp):
     """The 256-image batch at its full sizes (sides log-uniform 512..4096,
     about 1 Gpx), run as bench.py runs it: parameters tuned on the largest
-    image, one plan, launched as a HIP graph and replayed.  Every image is
-    checked for J <= R <= I after each replay; 16 images (the smallest, the
-    largest and 14 drawn at random) are compared with the oracle bit for bit,
-    after the second replay."""
+    image, one plan, launched as a HIP graph and replayed twice.  After each
+    replay every one of the 256 images is compared whole with the oracle's
+    result (digests)."""
     import torch
 
+    g = golden()
     announce("c4 256 images: generating")
     pairs = synth.c4()
+    for k, (I, J) in enumerate(pairs):
+        _check_inputs(g, "c4/%d" % k, I, J)
     dev = torch.device("cuda:0")
     pristine = [torch.from_numpy(J).to(dev) for I, J in pairs]
     masks = [torch.from_numpy(I).to(dev) for I, J in pairs]
@@ -143,21 +172,29 @@ def test_c4_full_batch_sampled(iwpp):
             plan.launch(graph=True)
             st = plan.status()
             assert st["rc"] == iwpp.OK and st["images"] == 256
-            for k, (w, p, m) in enumerate(zip(work, pristine, masks)):
-                assert bool((w >= p).all()) and bool((w <= m).all()), "image %d" % k
+            bad = [k for k, w in enumerate(work)
+                   if synth.sha256(w.cpu().numpy()) != g["c4/%d" % k]["R"]]
+            if bad:
+                I, J = pairs[bad[0]]
+                rc, R = oracle.reconstruct(J, I, 8)
+                assert rc == oracle.OK
+                raise AssertionError("replay %d: %d images differ (%s); image %d: %s" % (
+                    replay, len(bad), bad[:8], bad[0],
+                    _first_difference(work[bad[0]].cpu().numpy(), R)))
     finally:
         plan.close()
-    rng = np.random.default_rng(5)
-    small = min(range(len(masks)), key=lambda k: masks[k].numel())
-    picks = sorted({small, big} | set(int(k) for k in rng.choice(len(pairs), 14, replace=False)))
-    for k in picks:
-        I, J = pairs[k]
-        announce("c4 image %d (%dx%d): oracle" % (k, I.shape[0], I.shape[1]))
-        rc, R = oracle.reconstruct(J, I, 8)
-        assert rc == oracle.OK
-        got = work[k].cpu().numpy()
-        bad = got != R
-        if bad.any():
-            y, x = np.argwhere(bad)[0]
-            raise AssertionError("image %d: %d pixels differ, first at (%d, %d): got %d want %d"
-                                 % (k, bad.sum(), y, x, got[y, x], R[y, x]))
+
+
+def test_c1_c2_full_size_digests(iwpp):
+    """The two small configurations through the plain single-image call, with
+    the library defaults, against the stored digests."""
+    import torch
+
+    g = golden()
+    dev = torch.device("cuda:0")
+    for name, (I, J) in (("c1", synth.c1()), ("c2", synth.c2())):
+        _check_inputs(g, name, I, J)
+        announce("%s %dx%d: GPU reconstruction" % (name, I.shape[0], I.shape[1]))
+        Jt = torch.from_numpy(J).to(dev)
+        iwpp.reconstruct(Jt, torch.from_numpy(I).to(dev), 8)
+        assert synth.sha256(Jt.cpu().numpy()) == g[name]["R"], name
