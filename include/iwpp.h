@@ -68,6 +68,9 @@ extern "C" {
 #define IWPP_E_INTERNAL (-7)        /* a bounded device wait ran out        */
 #define IWPP_E_TIMEOUT (-8)         /* server wait timed out                */
 #define IWPP_E_UNSUPPORTED (-9)     /* parameter combination not compiled   */
+#define IWPP_E_SCRATCH (-10)        /* iwpp_reconstruct_noalloc: the image
+                                       needs more workspace than its static
+                                       array holds                         */
 
 /* ---- element types ---- */
 #define IWPP_U8 0
@@ -302,6 +305,37 @@ int iwpp_fill_holes_async(const void *image, void *out, int64_t H, int64_t W, in
 int iwpp_edt_async(const void *image, int64_t ld_image, void *sites, void *dist2,
                    int64_t ld_out, int64_t H, int64_t W, int conn, const iwpp_params *params,
                    iwpp_stream_t stream);
+
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the single-image
+ * reconstruction of iwpp_reconstruct_async (same kernels, same result),
+ * asynchronous on `stream`, allocating nothing.  Its library workspace
+ * (control block, per-tile state and first-visit flags, tile-queue rings,
+ * packed side columns) is carved from one static device array of
+ * IWPP_NOALLOC_SCRATCH_BYTES (128 MiB) that every device the library runs on
+ * holds until the process ends; its address is looked up once per device, on
+ * the first call with that device current.  An image whose workspace would
+ * not fit returns IWPP_E_SCRATCH before any GPU work (about 265 bytes per
+ * 64 x 64 uint8 tile and 521 bytes per 64 x 32 int32 tile, plus the queue
+ * rings of up to 8192 workgroups: up to about 2 Gpx uint8 or 0.5 Gpx int32).
+ *   img, dtype, conn, flags, params: as for iwpp_reconstruct_async; the
+ *     autotuner's stored values are not consulted, and only mode 0 (the
+ *     persistent kernel) is accepted (others return IWPP_E_UNSUPPORTED);
+ *     params->timing is ignored.
+ *   status: device pointer to one int32 owned by the caller (may be NULL);
+ *     when the reconstruction has finished on `stream`, it holds the IWPP_*
+ *     status the existing entry point reports (IWPP_OK, _MARKER_GT_MASK,
+ *     _INCOMPLETE or _INTERNAL).
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: the call clears what must start at zero itself (with a
+ * kernel, no memset), and calls that overlap on one device (other streams,
+ * other threads) race and must not be issued.  Returns IWPP_OK once queued,
+ * or a host-side argument error.
+ */
+#define IWPP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int iwpp_reconstruct_noalloc(const iwpp_image *img, int dtype, int conn, uint32_t flags,
+                             const iwpp_params *params, int32_t *status, iwpp_stream_t stream);
 
 /*
  * Plain device-to-device streaming copy of `bytes` (a multiple of 16) with

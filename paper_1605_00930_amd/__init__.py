@@ -27,6 +27,7 @@ E_BUDGET = -6
 E_INTERNAL = -7
 E_TIMEOUT = -8
 E_UNSUPPORTED = -9
+E_SCRATCH = -10
 U8, I32 = 0, 1
 FLAG_CLAMP_MARKER = 1
 FLAG_EROSION = 2
@@ -108,6 +109,7 @@ def _load():
         "iwpp_server_destroy": ([vp], i32),
         "iwpp_release_workspace": ([], i32),
         "iwpp_device_copy": ([vp, vp, ctypes.c_size_t, vp], i32),
+        "iwpp_reconstruct_noalloc": ([P(Image), i32, i32, u32, P(Params), vp, vp], i32),
         "iwpp_fill_holes_async": ([vp, vp, i64, i64, i64, i32, i32, P(Params), vp], i32),
         "iwpp_edt_async": ([vp, i64, vp, vp, i64, i64, i64, i32, P(Params), vp], i32),
     }
@@ -194,6 +196,26 @@ def reconstruct_async(marker, mask, conn: int = 8, *, clamp: bool = False,
                                         _ptr(_params(params)), _stream_handle(stream))
     if rc != OK:
         raise IwppError(rc, "iwpp_reconstruct_async")
+
+
+def reconstruct_noalloc(marker, mask, conn: int = 8, *, status=None, clamp: bool = False,
+                        erosion: bool = False, params=None, stream=None) -> None:
+    """Queue R_mask(marker) in place on `stream` through the entry point that
+    allocates nothing (its workspace is a static device array).  `status`, if
+    given, is a one-element int32 tensor on the marker's device that receives
+    the call's IWPP status when the work has finished on the stream."""
+    import torch
+
+    im, dt = _image(marker, mask)
+    sp = None
+    if status is not None:
+        if status.dtype != torch.int32 or status.numel() < 1 or status.device != marker.device:
+            raise ValueError("status must be an int32 tensor on the marker's device")
+        sp = status.data_ptr()
+    rc = _load().iwpp_reconstruct_noalloc(ctypes.byref(im), dt, conn, _flags(clamp, erosion),
+                                          _ptr(_params(params)), sp, _stream_handle(stream))
+    if rc != OK:
+        raise IwppError(rc, "iwpp_reconstruct_noalloc")
 
 
 def stream_status(stream=None, *, check: bool = True) -> dict:

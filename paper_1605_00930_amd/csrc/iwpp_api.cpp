@@ -103,8 +103,11 @@ namespace iwpp {
 
 int default_tile_h(int dtype) { return dtype == IWPP_U8 ? 64 : 32; }
 
-// Resolve user params (NULL / zero fields) against tuned and default values.
-Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W) {
+// Resolve user params (NULL / zero fields) against tuned and default values
+// (with `tuned` false the autotuner's table is not consulted: the defaults
+// and the user's values only).
+Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W,
+                        bool tuned) {
   Resolved r{};
   iwpp_params base{};
   base.tile_h = default_tile_h(dtype);
@@ -116,7 +119,7 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   // straight to rounds of passes; int32 (h-dome): short fronts, few seeds
   base.seed_queue = dtype == IWPP_U8 ? -1 : 8;
   base.queue_waves = 4;
-  {
+  if (tuned) {
     std::lock_guard<std::mutex> g(g_mu);
     load_tune_cache_locked();
     auto it = g_tuned.find({dtype, conn, size_class(H, W)});
@@ -390,11 +393,17 @@ int plan_queues(const Variant& v, const Resolved& rp, int64_t ntiles, int nimg,
                 const DevImage& one, int* grid, KParams* kp) {
   int rc = device_grid(v, ntiles, rp.grid, grid);
   if (rc) return rc;
-  kp->nq = *grid < kMaxQueues ? *grid : kMaxQueues;
+  return plan_queues_for_grid(*grid, ntiles, nimg, one, kp);
+}
+
+// Queue count, chunk and ring capacity of a persistent launch of `grid`
+// workgroups.
+int plan_queues_for_grid(int grid, int64_t ntiles, int nimg, const DevImage& one, KParams* kp) {
+  kp->nq = grid < kMaxQueues ? grid : kMaxQueues;
   kp->chunk = (int32_t)queue_chunk(ntiles, kp->nq, nimg, one.tiles_x, one.tiles_y);
   const int64_t nchunks = (ntiles + kp->chunk - 1) / kp->chunk;
   const int64_t per_q = (nchunks + kp->nq - 1) / kp->nq * kp->chunk;
-  const int64_t qcap = per_q + *grid + 64;
+  const int64_t qcap = per_q + grid + 64;
   if (qcap * kp->nq >= (int64_t(1) << 31)) return IWPP_E_ARG;
   kp->qcap = (uint32_t)qcap;
   return IWPP_OK;
@@ -690,6 +699,7 @@ const char* iwpp_strerror(int code) {
     case IWPP_E_INTERNAL: return "internal error: a bounded device wait ran out";
     case IWPP_E_TIMEOUT: return "timed out";
     case IWPP_E_UNSUPPORTED: return "parameter combination not supported";
+    case IWPP_E_SCRATCH: return "image needs more workspace than the static array holds";
     default: return "unknown status";
   }
 }

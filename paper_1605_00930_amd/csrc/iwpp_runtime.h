@@ -64,7 +64,8 @@ struct Buffers {
   void release();
 };
 
-Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W);
+Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H, int64_t W,
+                        bool tuned = true);
 int check_params(const iwpp_params* p);
 int check_image(const iwpp_image* im, int dtype);
 int check_common(int dtype, int conn, uint32_t flags);
@@ -72,6 +73,9 @@ DevImage make_dev_image(const iwpp_image& im, int tile_h, int64_t tile_base);
 int device_grid(const Variant& v, int64_t ntiles, int want, int* grid);
 int plan_queues(const Variant& v, const Resolved& rp, int64_t ntiles, int nimg,
                 const DevImage& one, int* grid, KParams* kp);
+int plan_queues_for_grid(int grid, int64_t ntiles, int nimg, const DevImage& one, KParams* kp);
+uint32_t flip_of(uint32_t flags);
+void order_for(uint32_t seed, int64_t ntiles, uint32_t* mul, uint32_t* add);
 int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& one,
             const DevImage* d_imgs, int nimg, int64_t ntiles, hipStream_t st, int64_t* launches);
 int status_of(const DevCtl& c, uint32_t flags, bool incomplete_rounds);

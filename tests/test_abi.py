@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_status_strings(lib):
     assert lib.iwpp_version() >= 10000
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         assert lib.iwpp_strerror(code)
     assert lib.iwpp_strerror(-2) == b"marker exceeds mask at some pixel"
 
@@ -99,3 +99,31 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(iwpp, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         iwpp._load()
+
+
+def test_noalloc_host_checks_before_gpu_work(lib):
+    """iwpp_reconstruct_noalloc (the entry point for callers that cannot
+    allocate) rejects bad arguments and images whose workspace exceeds its
+    static array on the host, before any device call."""
+    import paper_1605_00930_amd as iwpp
+
+    buf = ctypes.create_string_buffer(64)
+    other = ctypes.create_string_buffer(64)
+    a, b = ctypes.addressof(buf), ctypes.addressof(other)
+    f = lib.iwpp_reconstruct_noalloc
+
+    def call(H, W, dtype=iwpp.U8, conn=8, mask=None, mode=0):
+        im = iwpp.Image(a, b if mask is None else mask, H, W, 0)
+        p = iwpp.Params()
+        p.mode = mode
+        return f(ctypes.byref(im), dtype, conn, 0, ctypes.byref(p), None, None)
+
+    assert call(0, 5) == iwpp.E_ARG
+    assert call(5, 5, conn=6) == iwpp.E_ARG
+    assert call(5, 5, dtype=7) == iwpp.E_ARG
+    assert call(5, 5, mode=1) == iwpp.E_UNSUPPORTED
+    assert call(5, 5, mode=2) == iwpp.E_UNSUPPORTED
+    far = b + (1 << 40)  # never dereferenced: the size check comes first
+    assert call(40000, 40000, dtype=iwpp.I32, mask=far) == iwpp.E_SCRATCH
+    assert call(16384, 32768, dtype=iwpp.I32, mask=far) == iwpp.E_SCRATCH
+    assert call(65536, 65536, mask=far) == iwpp.E_SCRATCH
