@@ -166,9 +166,22 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
 // finished neighbours.
 __device__ __forceinline__ int64_t phase_tile(int64_t tx, int64_t ty, int64_t i) {
   const int64_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
-  const int64_t n[4] = {ey * ex, ey * ox, oy * ex, oy * ox};
+  // the group sizes, compared one after the other (no indexed array: that
+  // would live in scratch memory)
+  const int64_t n0 = ey * ex, n1 = ey * ox, n2 = oy * ex;
   int p = 0;
-  while (p < 3 && i >= n[p]) i -= n[p++];
+  if (i >= n0) {
+    i -= n0;
+    p = 1;
+    if (i >= n1) {
+      i -= n1;
+      p = 2;
+      if (i >= n2) {
+        i -= n2;
+        p = 3;
+      }
+    }
+  }
   const int64_t w = (p & 1) ? ox : ex;
   return (2 * (i / w) + (p >> 1)) * tx + 2 * (i % w) + (p & 1);
 }
@@ -226,21 +239,85 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
   }
 }
 
-// Turn ticket h of queue q into a tile id, or -1 when the launch is over.
-// Waits use relaxed loads only: an acquire on gfx950 invalidates the L2 of
-// the XCD, which a waiting worker must not do to the tiles others are
-// working on.
-static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
-                                     const uint8_t* visited, const DevImage* imgs, int q,
-                                     int grid, uint32_t h,
-                                     bool& first_pass, bool& ready, int& vbits) {
+// Per-worker state of the queue protocol.
+//  - First pass: the positions of queue q's first pass are dealt to the
+//    workers that serve q in turn (worker r of m takes r, r + m, ...), so a
+//    first-pass visit takes no ticket: no atomic on the queue head.
+//  - Ring tickets (re-activated tiles) come from the queue head, which starts
+//    at the first pass's length.
+//  - Pending count: a release of a tile is not taken off the launch's
+//    pending count at once.  It becomes this worker's credit, which covers
+//    the next tile it activates; the rest is taken off only when the worker
+//    is about to wait for work.  The count then never falls below the number
+//    of tiles queued or running (a tile is counted before it is queued), and
+//    it reaches zero exactly when every worker waits with no credit left: the
+//    worker whose subtraction brings it there ends the launch.  A visit thus
+//    touches the one pending word only when it activates more tiles than its
+//    credit covers, instead of on every visit (a single hot word serialises
+//    its atomics device-wide).
+struct QState {
+  int64_t fp_next;  // lane 0: this worker's next position in its queue's first pass
+  int64_t fp_step;  // workers serving the queue
+  uint32_t pre;     // lane 0: a ring ticket taken ahead of time, or kNoTicket
+  uint32_t credit;  // wave-uniform: releases not yet taken off the pending count
+  bool backlog;     // lane 0: its last ring slot was already filled when it looked
+};
+
+constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
+constexpr int kLaunchDone = -2;  // take_tile: this worker's credit ended the launch
+
+__device__ __forceinline__ QState init_qstate(const KParams& kp, int grid) {
+  QState s;
+  const int q = blockIdx.x % kp.nq;
+  s.fp_next = blockIdx.x / kp.nq;
+  s.fp_step = (grid - q + kp.nq - 1) / kp.nq;
+  s.pre = kNoTicket;
+  s.credit = 0;
+  s.backlog = false;
+  return s;
+}
+
+// Take a ticket of queue head *p (one lane).  The compiler combines the lanes
+// of an atomic with a wavefront-uniform address into one atomic and waits
+// for its result at once, to hand each lane its share; an address offset
+// that it cannot prove uniform (a zero written by an asm move) keeps the
+// plain atomic, whose round trip then overlaps the work before the ticket
+// is used.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t* p) {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return atomicAdd(p + z, 1u);
+}
+
+// Lane 0: the next tile of queue q for this worker, -1 when the launch is
+// over, or kLaunchDone when this worker's credit brought the pending count
+// to zero (the caller then ends the launch).  `first_pass` tells whether it
+// came from the first pass; `ready` whether it did not wait; `vbits` holds
+// the tile's first-visit bit (bit 0) and whether the packed side columns of
+// the tiles on either side are written (bits 1, 2).  Waits use relaxed
+// loads only: an acquire on gfx950 invalidates the L2 of the XCD, which a
+// waiting worker must not do to the tiles others are working on.
+static __device__ __forceinline__ int take_tile(DevCtl* ctl, int* queue, const KParams& kp,
+                                                uint32_t* state, const uint8_t* visited,
+                                                const DevImage* imgs, int q, int grid,
+                                                QState& qs, bool& first_pass, bool& ready,
+                                                int& vbits) {
   const int64_t len = first_pass_len(kp, q);
+  first_pass = false;
+  ready = false;
+  vbits = 0;
   int v;
-  first_pass = (int64_t)h < len;
-  ready = first_pass;
-  if (first_pass) {
-    v = (int)first_pass_tile(kp, imgs, q, h);
+  if (qs.pre == kNoTicket && qs.fp_next < len) {
+    first_pass = ready = true;
+    v = (int)first_pass_tile(kp, imgs, q, qs.fp_next);
+    qs.fp_next += qs.fp_step;
   } else {
+    uint32_t h = qs.pre;
+    qs.pre = kNoTicket;
+    if (h == kNoTicket) {
+      if (ld_rlx_u32(&ctl->done.v)) return -1;
+      h = take_ticket(&ctl->head[q].v);
+    }
     int* slot = ring_slot(queue, kp, q, h, len);
     uint32_t nap = 1;
     for (uint32_t w = 0;; ++w) {
@@ -250,6 +327,12 @@ static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, co
         break;
       }
       if (v == kSlotStop) return -1;
+      if (w == 0 && qs.credit) {
+        // about to wait: this worker's releases come off the pending count
+        const uint32_t c = qs.credit;
+        qs.credit = 0;
+        if (atomicSub(&ctl->pending.v, c) == c) return kLaunchDone;
+      }
       if ((w & 63) == 63 && ld_rlx_u32(&ctl->done.v)) return -1;
       if (w > kp.spin_limit) {
         abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
@@ -285,18 +368,29 @@ static __device__ __forceinline__ int resolve_ticket(DevCtl* ctl, int* queue, co
   return v;
 }
 
-constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
-
-// Take a ticket of queue head *p (one lane).  The compiler combines the lanes
-// of an atomic with a wavefront-uniform address into one atomic and waits
-// for its result at once, to hand each lane its share; an address offset
-// that it cannot prove uniform (a zero written by an asm move) keeps the
-// plain atomic, whose round trip then overlaps the work before the ticket
-// is used.
-__device__ __forceinline__ uint32_t take_ticket(uint32_t* p) {
-  uint32_t z;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-  return atomicAdd(p + z, 1u);
+// Whole wavefront: take the next tile (lane 0 does the work; the result,
+// the flags and the credit are broadcast).  Returns the tile, -1 when the
+// launch is over (after ending it, if this worker's credit did).
+static __device__ __forceinline__ int next_tile(DevCtl* ctl, int* queue, const KParams& kp,
+                                                uint32_t* state, const uint8_t* visited,
+                                                const DevImage* imgs, int q, int grid,
+                                                QState& qs, bool& first_pass, int& vbits) {
+  int t = 0, fp = 0, fv = 0;
+  if (threadIdx.x == 0) {
+    bool f = false, ready = false;
+    t = take_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, f, ready, fv);
+    qs.backlog = !f && ready;
+    fp = f ? 1 : 0;
+  }
+  t = __builtin_amdgcn_readfirstlane(t);
+  qs.credit = __builtin_amdgcn_readfirstlane(qs.credit);
+  first_pass = __builtin_amdgcn_readfirstlane(fp) != 0;
+  vbits = __builtin_amdgcn_readfirstlane(fv);
+  if (t == kLaunchDone) {
+    stop_all(ctl, queue, kp, grid);
+    return -1;
+  }
+  return t;
 }
 
 // Mid-visit requests.  peek_request() reads the state word of the tile a
@@ -321,25 +415,6 @@ __device__ __forceinline__ bool take_request(uint32_t* word, uint32_t peeked) {
   return true;
 }
 
-// Take a tile id from queue q (using an already taken ticket if `pre` holds
-// one), or -1 when the launch is over.
-static __device__ __forceinline__ int queue_pop(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state,
-                                const uint8_t* visited, const DevImage* imgs, int q, int grid,
-                                uint32_t pre,
-                                bool& first_pass, uint32_t& ticket, bool& ready,
-                                int& vbits) {
-  first_pass = false;
-  ready = false;
-  vbits = 0;
-  if (pre == kNoTicket) {
-    if (ld_rlx_u32(&ctl->done.v)) return -1;
-    pre = take_ticket(&ctl->head[q].v);
-  }
-  ticket = pre;
-  return resolve_ticket(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, ready,
-                        vbits);
-}
-
 // Gray-level bands: remember that tile t has work of class c for a later
 // launch (one lane; its class is already recorded).  The tile enters the
 // next launch's list once.
@@ -351,36 +426,36 @@ static __device__ void defer_tile(DevCtl* ctl, const KParams& kp, int t, int c) 
   atomicMax((int*)&ctl->max_deferred.v, c);
 }
 
-// While queue q's first pass lasts, the next ticket is taken before the
-// current tile is solved, so its round trip overlaps useful work (a first-
-// pass ticket maps to a tile without waiting).
-static __device__ __forceinline__ uint32_t prefetch_ticket(DevCtl* ctl, const KParams& kp, int q, int grid,
-                                           uint32_t last, bool backlog) {
-  // Decided without reading anything (a read here would stall the wavefront
-  // before its solve): take the ticket when this worker's last ticket was
-  // far enough inside the queue's first pass that the next one most likely
-  // is too, or when its last ring slot was already filled when it looked (a
-  // backlog: the next slot will not keep the ticket waiting either).  A
-  // ticket taken after the launch ended still returns: the slot wait checks
-  // the done flag.
-  const int64_t per_queue = grid / kp.nq + 1;
-  if (!backlog && (int64_t)last + 2 * per_queue >= first_pass_len(kp, q)) return kNoTicket;
-  return take_ticket(&ctl->head[q].v);
+// Once this worker's share of the first pass is done: if its last ring slot
+// was already filled when it looked (a backlog), the next ring ticket is
+// taken before the current tile is solved, so its round trip overlaps useful
+// work (lane 0).  Decided without reading anything: a read here would stall
+// the wavefront before its solve.  A ticket taken after the launch ended
+// still returns: the slot wait checks the done flag.
+static __device__ __forceinline__ void prefetch_ring_ticket(DevCtl* ctl, const KParams& kp, int q,
+                                                            QState& qs) {
+  if (qs.pre == kNoTicket && qs.backlog && qs.fp_next >= first_pass_len(kp, q))
+    qs.pre = take_ticket(&ctl->head[q].v);
 }
 
 // Publish the end of a visit of tile t (whole wavefront, once the tile's
-// marker write-back is complete).  Lanes 0..8
-// ask the neighbours in `act` for a visit while lane 9 tries to release t
-// (one round trip); then the pending count and the queue reservations of the
-// neighbours that were idle go out together (a second round trip), and only
-// after both have landed are the queue slots filled, so a queued tile is
-// always already counted.  Returns 1 if t must be run again (a neighbour
-// asked while it ran), 2 if this visit completed the launch, 0 otherwise.
+// marker write-back is complete).  Lanes 0..8 ask the neighbours in `act`
+// for a visit while lane 9 tries to release t (one round trip).  A release
+// adds to the worker's credit (QState); the neighbours that were idle are
+// covered by that credit, and only what it does not cover is added to the
+// pending count, together with their queue reservations (a second round
+// trip, only when there are such neighbours).  The queue slots are filled
+// once both have landed, so a queued tile is always already counted.
+// Returns 1 if t must be run again (a neighbour asked while it ran), else 0.
 // With `release` false (a visit that publishes its border and goes on) t
-// stays running and only the requests go out; that returns 0.
+// stays running and only the requests go out.  With `requeue`, a tile that a
+// neighbour asked for while it ran goes back on its queue instead of being
+// run again by this worker (it stays counted as pending, and its state word
+// keeps the request until the next owner takes it).
 static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
                        const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
-                       WorkerStats& ws, bool release = true) {
+                       WorkerStats& ws, uint32_t& credit, bool release = true,
+                       bool requeue = false) {
   const int d = threadIdx.x;
   int n = -1;
   if (d < 9 && ((act >> d) & 1u)) {
@@ -390,6 +465,7 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
   }
   bool fresh = false;  // was idle: this wavefront enqueues it
   bool released = false;
+  bool again = false;  // lane 9: t goes back on its queue
   if (n >= 0) {
     // with bands every request records its class on the tile, so that a
     // listed tile whose first-pass visit is still ahead knows it has work
@@ -405,28 +481,41 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
     uint32_t expect = TS_RUNNING;
     released = __hip_atomic_compare_exchange_strong(
         &state[t], &expect, 0u, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!released && requeue) {
+      again = true;
+      n = t;
+    }
   }
   const int nfresh = __popcll(__ballot(fresh));
   const bool rel = __ballot(released) != 0;
-  // count the new tiles and reserve their queue positions
-  const int delta = nfresh - (rel ? 1 : 0);
-  int last = 0;
-  if (d == 0 && delta != 0) {
-    const int old = atomicAdd((int*)&ctl->pending.v, delta);
-    last = old + delta == 0;
+  const bool req = __ballot(again) != 0;
+  // count the new tiles (what the credit does not cover) and reserve their
+  // queue positions
+  uint32_t cr = credit + (rel ? 1u : 0u);
+  uint32_t add = 0;
+  if ((uint32_t)nfresh > cr) {
+    add = (uint32_t)nfresh - cr;
+    cr = 0;
+  } else {
+    cr -= (uint32_t)nfresh;
   }
+  credit = cr;
+  if (d == 0 && add) atomicAdd(&ctl->pending.v, add);
   uint32_t pos = 0;
   int q = 0;
-  if (fresh) {
+  if (fresh || again) {
     q = queue_of(kp, n);
     pos = atomicAdd(&ctl->tail[q].v, 1u);
   }
-  int res = __builtin_amdgcn_readfirstlane(last) ? 2 : 0;
-  if (fresh)
+  // the count has landed before any slot is filled
+  if (add) drain_memory();
+  int res = 0;
+  if (fresh || again)
     __hip_atomic_store(ring_slot(queue, kp, q, pos, first_pass_len(kp, q)), n, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-  ws.requeued += nfresh;
-  if (release && !rel) {
+  ws.requeued += nfresh + (req ? 1 : 0);
+  if (req) ws.reproc++;
+  if (release && !rel && !req) {
     // running | pending: take the request and run again (the failed release
     // already saw the request, so the halo reads that follow see the
     // neighbour's new border)
@@ -438,6 +527,141 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
     res = 1;
   }
   return res;
+}
+
+// Geometry of tile t: its image and the origin of the tile in it.
+struct TilePos {
+  DevImage im;
+  int64_t ty, tx, y0, x0;
+};
+template <int TH>
+__device__ __forceinline__ TilePos tile_pos(const DevImage& one, const DevImage* imgs,
+                                            const KParams& kp, int t) {
+  TilePos p;
+  // two plain assignments: a select between the two sources would make the
+  // compiler copy `one` to scratch and read either through a flat pointer
+  if (imgs)
+    p.im = imgs[image_of(kp, imgs, t)];
+  else
+    p.im = one;
+  const int64_t tl = (int64_t)t - p.im.tile_base;
+  p.ty = tl / p.im.tiles_x;
+  p.tx = tl % p.im.tiles_x;
+  p.y0 = p.ty * TH;
+  p.x0 = p.tx * TW;
+  return p;
+}
+
+// The persistent worker of a tile policy that prefetches (TP::kPrefetch):
+// while tile t is solved, the next first-pass ticket is taken and the next
+// tile's state word exchanged to running; once t is solved, the next tile's
+// loads are issued into registers, before t is written back, drained and
+// published, so their round trip overlaps those steps.  A tile that a
+// neighbour asks for while it runs goes back on its queue (the registers
+// already hold the next tile) instead of being run again in place.  Only
+// plain launches use it: no gray-level bands, no visit limit.
+template <typename TP>
+__device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __restrict__ imgs,
+                                                const KParams& kp, DevCtl* ctl, int* queue,
+                                                uint32_t* state, uint8_t* visited) {
+  constexpr int TH = TP::kTH;
+  __shared__ typename TP::L s;
+  const bool lead = threadIdx.x == 0;
+  const int q = blockIdx.x % kp.nq;
+  const int grid = gridDim.x;
+  WorkerStats ws;
+  typename TP::Pre P;
+  QState qs = init_qstate(kp, grid);
+  const int64_t fp_len = first_pass_len(kp, q);
+  // Outer loop: take a tile the plain way (this worker's share of the first
+  // pass is done, or a ring ticket was taken ahead) and issue its loads.
+  // Inner loop: visit it; while the first pass has a next position for this
+  // worker, that tile's loads are issued once the current tile is solved,
+  // and its visit follows.  The registers of the next tile are written on
+  // every path into the write-back (zeros when there is none), so the
+  // compiler never keeps them live across a solve.
+  for (;;) {
+    uint32_t c0 = (uint32_t)now();
+    bool first_pass = false;
+    int fv = 0;
+    int t = next_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, first_pass, fv);
+    if (t < 0) break;
+    TilePos tp = tile_pos<TH>(one, imgs, kp, t);
+    TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
+    for (;;) {
+      uint32_t c1 = (uint32_t)now();
+      ws.t_idle += c1 - c0;
+      ws.visits++;
+      const bool first = (fv & 1) != 0;
+      const int sides = fv >> 1;
+      const bool viol = TP::commit(s, P, first, kp);
+      uint32_t c2 = (uint32_t)now();
+      ws.t_load += c2 - c1;
+      // the next tile, if this worker's share of the first pass has one: its
+      // state word (pending -> running) and its flags are taken now, and the
+      // round trip overlaps the solve
+      int nx = -1;
+      uint8_t f0 = 0, f1 = 0, f2 = 0;
+      uint32_t ended = 0;  // the launch was stopped (an abort): take no next tile
+      if (lead) {
+        ended = ld_rlx_u32(&ctl->done.v);
+        if (qs.fp_next < fp_len) {
+          nx = (int)first_pass_tile(kp, imgs, q, qs.fp_next);
+          qs.fp_next += qs.fp_step;
+          __hip_atomic_exchange(&state[nx], TS_RUNNING, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+          f0 = ld_coherent(&visited[nx]);
+          if (kp.colJ) {
+            if (nx > 0) f1 = ld_coherent(&visited[nx - 1]);
+            if (nx + 1 < kp.ntiles) f2 = ld_coherent(&visited[nx + 1]);
+          }
+        } else {
+          prefetch_ring_ticket(ctl, kp, q, qs);
+        }
+      }
+      VisitStats vs;
+      bool hit = false;
+      TP::solve(s, tp.y0, tp.x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves,
+                kp.spin_limit, vs, hit, &state[t], tp.im, kp, t, tp.tx, sides, false, false);
+      uint32_t c3 = (uint32_t)now();
+      ws.t_solve += c3 - c2;
+      nx = __builtin_amdgcn_readfirstlane(nx);
+      if (__builtin_amdgcn_readfirstlane(ended)) nx = -1;
+      int nfv = 0;
+      TilePos np = tp;
+      if (nx >= 0) {
+        // the exchange is complete before the tile is read (as at a pop)
+        drain_memory();
+        nfv = __builtin_amdgcn_readfirstlane((f0 == 0 ? 1 : 0) | (f1 ? 2 : 0) | (f2 ? 4 : 0));
+        np = tile_pos<TH>(one, imgs, kp, nx);
+        TP::issue(P, np.im, np.y0, np.x0, kp, nx, np.tx, nfv >> 1);
+      } else {
+        TP::clear_pre(P);
+      }
+      TP::store(s, tp.im, tp.y0, tp.x0, kp, t, first);
+      int amax = 0;
+      const uint32_t act = TP::activation_mask(s, tp.y0, tp.x0, false, amax);
+      uint32_t c4 = (uint32_t)now();
+      ws.t_store += c4 - c3;
+      ws.add(vs);
+      if (lead) {
+        if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
+        if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
+      }
+      // the write-back (and this tile's packed side columns) is complete
+      // before anyone is told about it
+      drain_memory();
+      if (lead && first) st_coherent(&visited[t], (uint8_t)1);
+      publish(ctl, queue, kp, state, t, tp.im, tp.ty, tp.tx, act, 0, ws, qs.credit, true, true);
+      c0 = (uint32_t)now();
+      ws.t_sync += c0 - c4;
+      if (nx < 0) break;
+      t = nx;
+      fv = nfv;
+      tp = np;
+    }
+  }
+  if (lead) ws.flush(ctl);
 }
 
 // The body of a persistent tile worker, for any tile policy TP (the
@@ -453,31 +677,18 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
   const int q = blockIdx.x % kp.nq;
   const int grid = gridDim.x;
   WorkerStats ws;
-  uint32_t pre = kNoTicket;  // lane 0: a ticket taken ahead of time
-  uint32_t last = 0;         // lane 0: the last ticket it took
-  bool backlog = false;      // lane 0: its last ring slot was filled when it looked
+  QState qs = init_qstate(kp, grid);
   for (;;) {
     uint32_t c0 = (uint32_t)now();
-    int t = 0, fp = 0, fv = 0;
-    if (lead) {
-      bool first_pass = false, ready = false;
-      t = queue_pop(ctl, queue, kp, state, visited, imgs, q, grid, pre, first_pass, last, ready,
-                    fv);
-      fp = first_pass ? 1 : 0;
-      backlog = !first_pass && ready;
-      pre = kNoTicket;
-    }
-    t = __builtin_amdgcn_readfirstlane(t);
-    fp = __builtin_amdgcn_readfirstlane(fp);
-    fv = __builtin_amdgcn_readfirstlane(fv);
+    bool fp = false;
+    int fv = 0;
+    const int t = next_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, fp, fv);
     uint32_t c1 = (uint32_t)now();
     ws.t_idle += c1 - c0;
     if (t < 0) break;
-    const int k = imgs ? image_of(kp, imgs, t) : 0;
-    const DevImage im = imgs ? imgs[k] : one;
-    const int64_t tl = (int64_t)t - im.tile_base;
-    const int64_t ty = tl / im.tiles_x, tx = tl % im.tiles_x;
-    const int64_t y0 = ty * TH, x0 = tx * TW;
+    const TilePos tp = tile_pos<TH>(one, imgs, kp, t);
+    const DevImage& im = tp.im;
+    const int64_t ty = tp.ty, tx = tp.tx, y0 = tp.y0, x0 = tp.x0;
     if (kp.band >= 0) {
       // gray-level bands: this visit takes the tile's deferred work (the
       // halo it loads holds it).  A list entry with nothing at or above the
@@ -492,8 +703,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
           defer_tile(ctl, kp, t, dc);
         }
         drain_memory();
-        const int res = publish(ctl, queue, kp, state, t, im, ty, tx, 0u, 0, ws);
-        if (res == 2) stop_all(ctl, queue, kp, grid);
+        const int res = publish(ctl, queue, kp, state, t, im, ty, tx, 0u, 0, ws, qs.credit);
         if (res != 1) continue;
         ws.visits--;  // a neighbour asked for the tile meanwhile: visit it after all
       }
@@ -507,7 +717,7 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
     const bool viol = TP::load(s, im, y0, x0, first, kp, t, tx, sides);
     uint32_t c2 = (uint32_t)now();
     ws.t_load += c2 - c1;
-    if (lead) pre = prefetch_ticket(ctl, kp, q, grid, last, backlog);
+    if (lead) prefetch_ring_ticket(ctl, kp, q, qs);
     // one solve and one publication site: a visit may go round this loop
     // after publishing its border early (streaming tiles) or after a
     // release that found a neighbour's request (re-run with the new halo)
@@ -544,8 +754,8 @@ __device__ __forceinline__ void persistent_worker(DevImage one, const DevImage* 
       // with `more` the border raised a neighbour before the tile's fixed
       // point: the requests go out now and the rounds go on
       const bool release = !(TP::kStreaming && more);
-      const int res = publish(ctl, queue, kp, state, t, im, ty, tx, act, cls, ws, release);
-      if (res == 2) stop_all(ctl, queue, kp, grid);
+      const int res =
+          publish(ctl, queue, kp, state, t, im, ty, tx, act, cls, ws, qs.credit, release);
       uint32_t c4 = (uint32_t)now();
       ws.t_sync += c4 - c3b;
       c3 = c4;

@@ -293,10 +293,18 @@ struct EdtTile {
     return d0 != 0;
   }
 
+  // No streaming publication and no prefetch of the next tile.
+  static constexpr bool kStreaming = false;
+  static constexpr bool kPrefetch = false;
+  struct Pre {};
+  __device__ static void issue(Pre&, const DevImage&, int64_t, int64_t, const KParams&, int64_t,
+                               int64_t, int) {}
+  __device__ static bool commit(L&, const Pre&, bool, const KParams&) { return false; }
+  __device__ static void clear_pre(Pre&) {}
+
   // Rounds until one changes nothing: the tile is then at a fixed point of
   // the propagation for its halo (the reconstruction tile's scan-round and
   // queue parameters do not apply).
-  static constexpr bool kStreaming = false;
   __device__ static bool solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
                                uint32_t iter_limit, VisitStats& vs, bool& hit_limit, uint32_t*,
                                const DevImage&, const KParams&, int64_t, int64_t, int, bool, bool) {

@@ -298,6 +298,101 @@ struct Tile {
     return __ballot(viol) != 0;
   }
 
+  // ---------------------------------------------------------- prefetch
+  // int32 tiles of 32 rows can hold the raw values of a whole tile and its
+  // halo in registers (two per row and lane, plus the side entries), so a
+  // worker issues the loads of its next tile before it writes back the
+  // current one: their round trip then overlaps the write-back, its drain and
+  // the publication, instead of following them.  issue() starts the loads;
+  // commit() stages the values in LDS as load() does.
+  static constexpr bool kPrefetch = sizeof(T) == 4 && TH == 32;
+  static constexpr int kSideEntries = 2 * TH + 4;
+  static constexpr int kSideRegs = (kSideEntries + 63) / 64;
+  struct Pre {
+    int j[G::ROWS], i[G::ROWS];
+    int ej[kSideRegs], ei[kSideRegs];
+  };
+
+  template <bool INNER>
+  __device__ __forceinline__ static void issue_t(Pre& p, const DevImage& im, int64_t y0,
+                                                 int64_t x0, const KParams& kp, int64_t t,
+                                                 int64_t tx, int sides) {
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    const gptr<const T> gI = (gptr<const T>)im.I;
+    const int lo_raw = in((T)LO, kp.flip);
+    const int64_t gx = x0 + lane();
+    const bool c_in = gx < im.W;
+#pragma unroll
+    for (int k = 0; k < G::ROWS; ++k) {
+      const int64_t gy = y0 - 1 + k;
+      p.j[k] = p.i[k] = lo_raw;
+      if (INNER || (gy >= 0 && gy < im.H && c_in)) {
+        p.j[k] = (int)ld_coherent(&gJ[gy * im.ld + gx]);
+        p.i[k] = (int)gI[gy * im.ld + gx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSideRegs; ++k) {
+      const int e = lane() + 64 * k;
+      p.ej[k] = p.ei[k] = lo_raw;
+      if (e < kSideEntries) side_load<INNER>(im, y0, x0, kp, t, tx, sides, e, p.ej[k], p.ei[k]);
+    }
+  }
+  __device__ __forceinline__ static void issue(Pre& p, const DevImage& im, int64_t y0, int64_t x0,
+                                               const KParams& kp, int64_t t, int64_t tx,
+                                               int sides) {
+    const bool inner = y0 >= 1 && y0 + TH < im.H && x0 >= 1 && x0 + TW < im.W;
+    if (inner)
+      issue_t<true>(p, im, y0, x0, kp, t, tx, sides);
+    else
+      issue_t<false>(p, im, y0, x0, kp, t, tx, sides);
+  }
+  __device__ __forceinline__ static void clear_pre(Pre& p) {
+#pragma unroll
+    for (int k = 0; k < G::ROWS; ++k) p.j[k] = p.i[k] = 0;
+#pragma unroll
+    for (int k = 0; k < kSideRegs; ++k) p.ej[k] = p.ei[k] = 0;
+  }
+  // Stage the issued values: J clamped to I (a clamped pixel's row is marked
+  // dirty), the complement of an erosion applied; returns true if a first
+  // visit saw J > I inside the tile.
+  __device__ __forceinline__ static bool commit(L& s, const Pre& p, bool first,
+                                                const KParams& kp) {
+    const uint32_t flip = kp.flip;
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    wsync();
+    bool viol = false;
+#pragma unroll
+    for (int yy = 0; yy < G::ROWS; ++yy) {
+      int a = in((T)p.j[yy], flip);
+      const int b = in((T)p.i[yy], flip);
+      if (a > b) {
+        if (yy >= 1 && yy <= TH) {
+          viol = viol || first;
+          s.rowdirty[yy - 1] = 1;
+        }
+        a = b;
+      }
+      s.J[yy * G::P + lane() + 1] = (T)a;
+      s.I[yy * G::P + lane() + 1] = (T)b;
+    }
+#pragma unroll
+    for (int k = 0; k < kSideRegs; ++k) {
+      const int e = lane() + 64 * k;
+      if (e >= kSideEntries) continue;
+      int y, x;
+      side_pos(e, y, x);
+      const int b = in((T)p.ei[k], flip);
+      const int a = imin(in((T)p.ej[k], flip), b);
+      s.J[G::at(y, x)] = (T)a;
+      s.I[G::at(y, x)] = (T)b;
+    }
+    wsync();
+    snapshot_border(s);
+    wsync();
+    return __ballot(viol) != 0;
+  }
+
   __device__ __forceinline__ static void snapshot_border(L& s) {
     s.b_top[lane()] = s.J[G::at(0, lane())];
     s.b_bot[lane()] = s.J[G::at(TH - 1, lane())];
@@ -1160,6 +1255,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   persistent_worker<Tile<T, CONN, TH>>(one, imgs, kp, ctl, queue, state, visited);
 }
 
+// The same worker with the next tile's loads in flight during the current
+// tile's write-back (32-row int32 tiles; plain launches only, see
+// prefetch_worker).
+template <typename T, int CONN, int TH>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_persistent_pf(
+    DevImage one, const DevImage* __restrict__ imgs, KParams kp, DevCtl* ctl, int* queue,
+    uint32_t* state, uint8_t* visited) {
+  if constexpr (Tile<T, CONN, TH>::kPrefetch)
+    prefetch_worker<Tile<T, CONN, TH>>(one, imgs, kp, ctl, queue, state, visited);
+}
+
 // ------------------------------------------------------------ host-driven rounds
 
 // One round: every active tile is visited once; tiles it activates are
@@ -1241,8 +1347,12 @@ __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uin
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0;
     __syncthreads();
-    if (threadIdx.x < kMaxQueues && queue && threadIdx.x < kp.nq)
+    // ring tickets and ring positions both start after the first pass, whose
+    // positions are dealt to the workers without tickets
+    if (threadIdx.x < kMaxQueues && queue && threadIdx.x < kp.nq) {
+      ctl->head[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
       ctl->tail[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
+    }
     if (threadIdx.x == 0) {
       ctl->pending.v = state ? (uint32_t)(kp.list_mode ? kp.list_len : kp.ntiles) : 0u;
       ctl->max_deferred.v = 0xFFFFFFFFu;  // -1: nothing deferred
@@ -1324,10 +1434,16 @@ hipError_t launch_persistent(const Variant& v, const DevImage& one, const DevIma
   if (v.dtype == kDtypeEdt)
     return launch_persistent_edt(v.conn, v.tile_h, one, kp, ctl, queue, state, visited, grid,
                                  st);
+  // plain launches of the tiles that prefetch take the prefetching worker
+  const bool pf = kp.band < 0 && kp.max_visits == 0;
 #define X(T, C, H)                                                                          \
   if (v.dtype == dtype_of((T*)nullptr) && v.conn == C && v.tile_h == H) {                   \
-    hipLaunchKernelGGL((k_persistent<T, C, H>), dim3(grid), dim3(kThreads), 0, st, one,     \
-                       imgs, kp, ctl, queue, state, visited);                               \
+    if (pf && Tile<T, C, H>::kPrefetch)                                                     \
+      hipLaunchKernelGGL((k_persistent_pf<T, C, H>), dim3(grid), dim3(kThreads), 0, st,     \
+                         one, imgs, kp, ctl, queue, state, visited);                        \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_persistent<T, C, H>), dim3(grid), dim3(kThreads), 0, st, one,   \
+                         imgs, kp, ctl, queue, state, visited);                             \
     return hipGetLastError();                                                               \
   }
   IWPP_VARIANTS(X)
