@@ -240,10 +240,18 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 }
 
 // Per-worker state of the queue protocol.
-//  - First pass: the positions of queue q's first pass are dealt to the
-//    workers that serve q in turn (worker r of m takes r, r + m, ...), so a
-//    first-pass visit takes no ticket: no atomic on the queue head.
-//  - Ring tickets (re-activated tiles) come from the queue head, which starts
+//  - First pass: the positions of queue q's first pass are taken in chunks
+//    of kFpChunk positions, one ticket (an atomic on the queue's first-pass
+//    head) per chunk, and the next chunk's ticket is taken when the last
+//    position of the current one is, so its round trip overlaps a visit.
+//    With m workers serving the queue, ticket h holds positions
+//    (h / m) m K + h % m + j m, j < K: the workers that took neighbouring
+//    tickets walk neighbouring positions in step, so the tiles in flight at
+//    one time stay a compact band of the pass's order (as one ticket per
+//    position would keep them), while there is one atomic per K positions.
+//    Tickets keep the first pass dynamic: a worker that is not resident yet
+//    (other work on the device) holds no positions.
+//  - Ring tickets (re-activated tiles) come from the ring head, which starts
 //    at the first pass's length.
 //  - Pending count: a release of a tile is not taken off the launch's
 //    pending count at once.  It becomes this worker's credit, which covers
@@ -255,22 +263,27 @@ static __device__ void abort_launch(DevCtl* ctl, int* queue, const KParams& kp, 
 //    touches the one pending word only when it activates more tiles than its
 //    credit covers, instead of on every visit (a single hot word serialises
 //    its atomics device-wide).
-struct QState {
-  int64_t fp_next;  // lane 0: this worker's next position in its queue's first pass
-  int64_t fp_step;  // workers serving the queue
-  uint32_t pre;     // lane 0: a ring ticket taken ahead of time, or kNoTicket
-  uint32_t credit;  // wave-uniform: releases not yet taken off the pending count
-  bool backlog;     // lane 0: its last ring slot was already filled when it looked
-};
-
 constexpr uint32_t kNoTicket = 0xFFFFFFFFu;
 constexpr int kLaunchDone = -2;  // take_tile: this worker's credit ended the launch
+constexpr uint32_t kFpChunk = 8;
+
+struct QState {
+  uint32_t fp_next, fp_left;  // lane 0: next position of the current chunk, positions left
+  uint32_t fp_step;           // workers serving the queue (m)
+  uint32_t fp_pre;            // lane 0: the next chunk's ticket, taken ahead, or kNoTicket
+  bool fp_done;              // lane 0: the queue's first pass has no chunk left
+  uint32_t pre;              // lane 0: a ring ticket taken ahead of time, or kNoTicket
+  uint32_t credit;           // wave-uniform: releases not yet taken off the pending count
+  bool backlog;              // lane 0: its last ring slot was already filled when it looked
+};
 
 __device__ __forceinline__ QState init_qstate(const KParams& kp, int grid) {
   QState s;
   const int q = blockIdx.x % kp.nq;
-  s.fp_next = blockIdx.x / kp.nq;
-  s.fp_step = (grid - q + kp.nq - 1) / kp.nq;
+  s.fp_next = s.fp_left = 0;
+  s.fp_step = (uint32_t)((grid - q + kp.nq - 1) / kp.nq);
+  s.fp_pre = kNoTicket;
+  s.fp_done = false;
   s.pre = kNoTicket;
   s.credit = 0;
   s.backlog = false;
@@ -287,6 +300,30 @@ __device__ __forceinline__ uint32_t take_ticket(uint32_t* p) {
   uint32_t z;
   asm volatile("v_mov_b32 %0, 0" : "=v"(z));
   return atomicAdd(p + z, 1u);
+}
+
+// Lane 0: this worker's next position in queue q's first pass (of length
+// len), or -1 once the first pass has none left.
+__device__ __forceinline__ int64_t next_first_pass(DevCtl* ctl, int q, int64_t len, QState& qs) {
+  if (qs.fp_left == 0 || qs.fp_next >= len) {
+    if (qs.fp_done) return -1;
+    const uint32_t h = qs.fp_pre != kNoTicket ? qs.fp_pre : take_ticket(&ctl->fphead[q].v);
+    qs.fp_pre = kNoTicket;
+    const int64_t m = qs.fp_step;
+    const int64_t a = (int64_t)(h / m) * m * kFpChunk + h % m;
+    if (a >= len) {
+      qs.fp_done = true;
+      return -1;
+    }
+    qs.fp_next = (uint32_t)a;
+    qs.fp_left = kFpChunk;
+  }
+  const int64_t pos = qs.fp_next;
+  qs.fp_next += qs.fp_step;
+  qs.fp_left--;
+  if ((qs.fp_left == 0 || qs.fp_next >= len) && qs.fp_pre == kNoTicket)
+    qs.fp_pre = take_ticket(&ctl->fphead[q].v);
+  return pos;
 }
 
 // Lane 0: the next tile of queue q for this worker, -1 when the launch is
@@ -307,10 +344,10 @@ static __device__ __forceinline__ int take_tile(DevCtl* ctl, int* queue, const K
   ready = false;
   vbits = 0;
   int v;
-  if (qs.pre == kNoTicket && qs.fp_next < len) {
+  const int64_t pos = qs.pre == kNoTicket ? next_first_pass(ctl, q, len, qs) : -1;
+  if (pos >= 0) {
     first_pass = ready = true;
-    v = (int)first_pass_tile(kp, imgs, q, qs.fp_next);
-    qs.fp_next += qs.fp_step;
+    v = (int)first_pass_tile(kp, imgs, q, pos);
   } else {
     uint32_t h = qs.pre;
     qs.pre = kNoTicket;
@@ -434,8 +471,7 @@ static __device__ void defer_tile(DevCtl* ctl, const KParams& kp, int t, int c) 
 // still returns: the slot wait checks the done flag.
 static __device__ __forceinline__ void prefetch_ring_ticket(DevCtl* ctl, const KParams& kp, int q,
                                                             QState& qs) {
-  if (qs.pre == kNoTicket && qs.backlog && qs.fp_next >= first_pass_len(kp, q))
-    qs.pre = take_ticket(&ctl->head[q].v);
+  if (qs.pre == kNoTicket && qs.backlog && qs.fp_done) qs.pre = take_ticket(&ctl->head[q].v);
 }
 
 // Publish the end of a visit of tile t (whole wavefront, once the tile's
@@ -605,9 +641,9 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       uint32_t ended = 0;  // the launch was stopped (an abort): take no next tile
       if (lead) {
         ended = ld_rlx_u32(&ctl->done.v);
-        if (qs.fp_next < fp_len) {
-          nx = (int)first_pass_tile(kp, imgs, q, qs.fp_next);
-          qs.fp_next += qs.fp_step;
+        const int64_t pos = qs.pre == kNoTicket ? next_first_pass(ctl, q, fp_len, qs) : -1;
+        if (pos >= 0) {
+          nx = (int)first_pass_tile(kp, imgs, q, pos);
           __hip_atomic_exchange(&state[nx], TS_RUNNING, __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
           f0 = ld_coherent(&visited[nx]);

@@ -26,8 +26,9 @@ struct alignas(128) HotWord {
   uint32_t pad[31];
 };
 struct DevCtl {
-  HotWord head[kMaxQueues];  // next ticket of each queue
-  HotWord tail[kMaxQueues];  // next fill position of each queue
+  HotWord fphead[kMaxQueues];  // next first-pass chunk of each queue
+  HotWord head[kMaxQueues];    // next ring ticket of each queue
+  HotWord tail[kMaxQueues];    // next fill position of each queue
   HotWord pending;           // tiles queued or running (int32)
   HotWord status;            // ST_* bits (int32)
   HotWord done;              // set once no more work can arrive

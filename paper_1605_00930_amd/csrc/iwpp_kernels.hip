@@ -519,6 +519,38 @@ struct Tile {
         }
         continue;
       }
+      if constexpr (sizeof(T) == 4) {
+        // int32 rows are written two pixels to a lane (8-byte stores, two
+        // rows to an instruction) when the image allows 8-byte accesses there
+        const bool wide4 = TH <= 32 && (im.ld % 2) == 0 && ((uintptr_t)im.J % 8) == 0 &&
+                           x0 + TW <= im.W;
+        if (wide4) {
+          constexpr int NQ = NR / 2;
+          const int c2 = 2 * (lane() & 31), rs = lane() >> 5;
+          const int64_t rows_in = im.H - (y0 + g);
+          // every value is read from LDS before the first store (see below)
+          uint64_t w[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int a = G::at(g + 2 * q + rs, c2);
+            w[q] = (uint64_t)(uint32_t)out(s.J[a], flip) |
+                   ((uint64_t)(uint32_t)out(s.J[a + 1], flip) << 32);
+          }
+          // this lane's rows: bit q for row 2 q + rs, dirty and inside the image
+          uint32_t mine = 0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+            mine |= (uint32_t)(((rows >> (2 * q)) >> rs) & 1ull & (2 * q + rs < rows_in)) << q;
+          gptr<uint64_t> row = (gptr<uint64_t>)((gptr<T>)im.J + (y0 + g + rs) * im.ld + x0 + c2);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            if ((mine >> q) & 1u) st_coherent(row, w[q]);
+            row = (gptr<uint64_t>)((gptr<T>)row + 2 * im.ld);
+            asm volatile("" : "+v"(row));
+          }
+          continue;
+        }
+      }
       // Every row's value is read from LDS before the first store: an LDS
       // read into a register that an outstanding store still reads would
       // make the store wait for completion (a store reads its registers
@@ -1347,9 +1379,10 @@ __global__ void k_init(KParams kp, DevCtl* ctl, int* queue, uint32_t* state, uin
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0;
     __syncthreads();
-    // ring tickets and ring positions both start after the first pass, whose
-    // positions are dealt to the workers without tickets
+    // first-pass chunks are counted from 0; ring tickets and ring positions
+    // both start after the first pass
     if (threadIdx.x < kMaxQueues && queue && threadIdx.x < kp.nq) {
+      ctl->fphead[threadIdx.x].v = 0u;
       ctl->head[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
       ctl->tail[threadIdx.x].v = (uint32_t)first_pass_len(kp, threadIdx.x);
     }
