@@ -610,7 +610,7 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
   QState qs = init_qstate(kp, grid);
   const int64_t fp_len = first_pass_len(kp, q);
   // Outer loop: take a tile the plain way (this worker's share of the first
-  // pass is done, or a ring ticket was taken ahead) and issue its loads.
+  // pass is done, or a ring ticket was taken ahead); its visit loads it.
   // Inner loop: visit it; while the first pass has a next position for this
   // worker, that tile's loads are issued once the current tile is solved,
   // and its visit follows.  The registers of the next tile are written on
@@ -623,14 +623,22 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
     int t = next_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, first_pass, fv);
     if (t < 0) break;
     TilePos tp = tile_pos<TH>(one, imgs, kp, t);
-    TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
+    // a re-visit stages its seams (load_seam); anything else is issued into
+    // the registers and committed at once
+    bool seam = false;
+    if constexpr (TP::kSeamVisits) seam = !(fv & 1) && kp.colJ;
+    if (!seam) TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
     for (;;) {
       uint32_t c1 = (uint32_t)now();
       ws.t_idle += c1 - c0;
       ws.visits++;
       const bool first = (fv & 1) != 0;
       const int sides = fv >> 1;
-      const bool viol = TP::commit(s, P, first, kp);
+      bool viol = false;
+      if (seam)
+        TP::load_seam(s, tp.im, tp.y0, tp.x0, kp, t, tp.tx, sides);
+      else
+        viol = TP::commit(s, P, first, kp);
       uint32_t c2 = (uint32_t)now();
       ws.t_load += c2 - c1;
       // the next tile, if this worker's share of the first pass has one: its
@@ -657,8 +665,9 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       }
       VisitStats vs;
       bool hit = false;
-      TP::solve(s, tp.y0, tp.x0, kp.sweeps, !first, kp.seed_queue_max, kp.queue_waves,
-                kp.spin_limit, vs, hit, &state[t], tp.im, kp, t, tp.tx, sides, false, false);
+      TP::template solve<TP::kSeamVisits>(s, tp.y0, tp.x0, kp.sweeps, !first, kp.seed_queue_max,
+                                          kp.queue_waves, kp.spin_limit, vs, hit, &state[t],
+                                          tp.im, kp, t, tp.tx, sides, false, false);
       uint32_t c3 = (uint32_t)now();
       ws.t_solve += c3 - c2;
       nx = __builtin_amdgcn_readfirstlane(nx);
@@ -695,6 +704,7 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       t = nx;
       fv = nfv;
       tp = np;
+      seam = false;
     }
   }
   if (lead) ws.flush(ctl);

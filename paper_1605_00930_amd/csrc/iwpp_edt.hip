@@ -301,10 +301,14 @@ struct EdtTile {
                                int64_t, int) {}
   __device__ static bool commit(L&, const Pre&, bool, const KParams&) { return false; }
   __device__ static void clear_pre(Pre&) {}
+  static constexpr bool kSeamVisits = false;
+  __device__ static void load_seam(L&, const DevImage&, int64_t, int64_t, const KParams&, int64_t,
+                                   int64_t, int) {}
 
   // Rounds until one changes nothing: the tile is then at a fixed point of
   // the propagation for its halo (the reconstruction tile's scan-round and
   // queue parameters do not apply).
+  template <bool SEAM = false>
   __device__ static bool solve(L& s, int64_t y0, int64_t x0, int, bool, int, uint32_t,
                                uint32_t iter_limit, VisitStats& vs, bool& hit_limit, uint32_t*,
                                const DevImage&, const KParams&, int64_t, int64_t, int, bool, bool) {

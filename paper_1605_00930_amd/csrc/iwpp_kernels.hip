@@ -96,6 +96,9 @@ struct Lds {
   uint32_t claim[G::NWORDS];  // pixels already in the next queue
   T b_top[TW], b_bot[TW], b_left[TH], b_right[TH];  // border as loaded
   uint8_t rowdirty[TH];
+  // seam visits (Tile::load_seam): tile rows staged so far (bit y, tiles of
+  // at most 32 rows) and the rows the next queue wave needs
+  uint32_t loaded, need;
 };
 
 // Queue entries are 15-bit pixel indices y * TW + x; bit 15 marks an entry
@@ -292,6 +295,9 @@ struct Tile {
       s.J[G::at(y, x)] = (T)a;
       s.I[G::at(y, x)] = (T)b;
     }
+    if constexpr (kSeamVisits) {
+      if (lane() == 0) s.loaded = kAllRows;
+    }
     wsync();
     snapshot_border(s);
     wsync();
@@ -387,10 +393,163 @@ struct Tile {
       s.J[G::at(y, x)] = (T)a;
       s.I[G::at(y, x)] = (T)b;
     }
+    if constexpr (kSeamVisits) {
+      if (lane() == 0) s.loaded = kAllRows;
+    }
     wsync();
     snapshot_border(s);
     wsync();
     return __ballot(viol) != 0;
+  }
+
+  // ---------------------------------------------------------- seam visits
+  // A re-visit starts from a tile at its fixed point for an older halo: only
+  // pixels next to the seams can rise at first, and typically only a few do,
+  // a pixel or two deep.  load_seam() stages just the seam ring -- the rows
+  // above, at the top of, at the bottom of and below the tile, the tile's
+  // own first and last columns (its packed side columns, written from its
+  // first visit on), the neighbours' facing columns and the corners -- and
+  // the queue then stages further rows only as its waves reach them
+  // (ensure_rows).  A visit that needs the whole tile (rounds of passes)
+  // stages the rest first.  Rows that are not staged are never read: queue
+  // entries and their neighbours lie on staged rows, the write-back covers
+  // dirty rows only, and the activation reads the ring.
+  static constexpr bool kSeamVisits = sizeof(T) == 4 && TH <= 32;
+  static constexpr uint32_t kAllRows = TH >= 32 ? 0xFFFFFFFFu : ((1u << TH) - 1);
+
+  __device__ __forceinline__ static void load_seam(L& s, const DevImage& im, int64_t y0,
+                                                   int64_t x0, const KParams& kp, int64_t t,
+                                                   int64_t tx, int sides) {
+    const uint32_t flip = kp.flip;
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    const gptr<const T> gI = (gptr<const T>)im.I;
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
+    wsync();
+    const int lo_raw = in((T)LO, flip);
+    const int64_t gx = x0 + lane();
+    const bool c_in = gx < im.W;
+    // halo row, first row, last row, halo row (halo coordinates)
+    constexpr int ring[4] = {0, 1, TH, TH + 1};
+    int j[4], i[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t gy = y0 + ring[k] - 1;
+      j[k] = i[k] = lo_raw;
+      if (gy >= 0 && gy < im.H && c_in) {
+        j[k] = (int)ld_coherent(&gJ[gy * im.ld + gx]);
+        i[k] = (int)gI[gy * im.ld + gx];
+      }
+    }
+    // the tile's own first and last columns: entry e < TH is column 0 of
+    // row e, the next TH column TW - 1
+    constexpr int KO = (2 * TH + 63) / 64;
+    int oj[KO], oi[KO];
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+      const int e = lane() + 64 * k;
+      const int side = e >= TH, r = side ? e - TH : e, x = side ? TW - 1 : 0;
+      oj[k] = oi[k] = lo_raw;
+      if (e < 2 * TH && y0 + r < im.H && x0 + x < im.W) {
+        oj[k] = (int)ld_coherent(&((gptr<const T>)kp.colJ)[side_at(t, side) + r]);
+        oi[k] = (int)ld_coherent(&((gptr<const T>)kp.colI)[side_at(t, side) + r]);
+      }
+    }
+    constexpr int NE = 2 * TH + 4;
+    constexpr int K = (NE + 63) / 64;
+    int ej[K], ei[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = lane() + 64 * k;
+      ej[k] = ei[k] = lo_raw;
+      if (e < NE) side_load<false>(im, y0, x0, kp, t, tx, sides, e, ej[k], ei[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = in((T)i[k], flip);
+      int a = in((T)j[k], flip);
+      if (a > b) {
+        if (ring[k] >= 1 && ring[k] <= TH) s.rowdirty[ring[k] - 1] = 1;
+        a = b;
+      }
+      s.J[ring[k] * G::P + lane() + 1] = (T)a;
+      s.I[ring[k] * G::P + lane() + 1] = (T)b;
+    }
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+      const int e = lane() + 64 * k;
+      if (e >= 2 * TH) continue;
+      const int side = e >= TH, r = side ? e - TH : e, x = side ? TW - 1 : 0;
+      const int b = in((T)oi[k], flip);
+      s.J[G::at(r, x)] = (T)imin(in((T)oj[k], flip), b);
+      s.I[G::at(r, x)] = (T)b;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = lane() + 64 * k;
+      if (e >= NE) continue;
+      int y, x;
+      side_pos(e, y, x);
+      const int b = in((T)ei[k], flip);
+      s.J[G::at(y, x)] = (T)imin(in((T)ej[k], flip), b);
+      s.I[G::at(y, x)] = (T)b;
+    }
+    if (lane() == 0) {
+      s.loaded = 1u | (1u << (TH - 1));
+      s.need = 0;
+    }
+    wsync();
+    snapshot_border(s);
+    wsync();
+  }
+
+  // Stage the tile rows in `need` (bit y) that are not staged yet, four at
+  // a time (their loads in flight together), and record them.
+  __device__ __forceinline__ static void ensure_rows(L& s, const DevImage& im, int64_t y0,
+                                                     int64_t x0, const KParams& kp,
+                                                     uint32_t need) {
+    uint32_t missing = need & ~__builtin_amdgcn_readfirstlane(s.loaded);
+    if (!missing) return;
+    const uint32_t flip = kp.flip;
+    const gptr<const T> gJ = (gptr<const T>)im.J;
+    const gptr<const T> gI = (gptr<const T>)im.I;
+    const int lo_raw = in((T)LO, flip);
+    const int64_t gx = x0 + lane();
+    const bool c_in = gx < im.W;
+    const uint32_t got = missing;
+    while (missing) {
+      constexpr int R = 4;
+      int r[R], j[R], i[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        r[k] = missing ? __builtin_ctz(missing) : -1;
+        missing &= missing - 1;
+        j[k] = i[k] = lo_raw;
+        const int64_t gy = y0 + r[k];
+        if (r[k] >= 0 && gy < im.H && c_in) {
+          j[k] = (int)ld_coherent(&gJ[gy * im.ld + gx]);
+          i[k] = (int)gI[gy * im.ld + gx];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        if (r[k] < 0) continue;
+        const int b = in((T)i[k], flip);
+        int a = in((T)j[k], flip);
+        if (a > b) {
+          s.rowdirty[r[k]] = 1;
+          a = b;
+        }
+        s.J[G::at(r[k], lane())] = (T)a;
+        s.I[G::at(r[k], lane())] = (T)b;
+      }
+    }
+    if (lane() == 0) s.loaded |= got;
+    wsync();
+  }
+  __device__ __forceinline__ static void ensure_all_rows(L& s, const DevImage& im, int64_t y0,
+                                                         int64_t x0, const KParams& kp) {
+    if constexpr (kSeamVisits)
+      ensure_rows(s, im, y0, x0, kp, kAllRows);
   }
 
   __device__ __forceinline__ static void snapshot_border(L& s) {
@@ -1094,8 +1253,12 @@ struct Tile {
   // overflow or after `waves` waves with receivers left (then sweep rounds
   // and a scan must follow: a front that winds through the tile is carried
   // further by one round of passes than by many queue waves).
+  // With `seam` (a seam visit), each wave first stages the rows its entries
+  // and their neighbours lie on.
   __device__ static bool queue_loop(L& s, int n, VisitStats& vs, uint32_t waves,
-                                    uint32_t iter_limit, bool& hit_limit) {
+                                    uint32_t iter_limit, bool& hit_limit, bool seam,
+                                    const DevImage& im, int64_t y0, int64_t x0,
+                                    const KParams& kp) {
     for (int w = lane(); w < G::NWORDS; w += 64) s.claim[w] = 0;
     wsync();
     for (uint32_t iter = 0;; ++iter) {
@@ -1108,6 +1271,20 @@ struct Tile {
       if (iter >= iter_limit) {
         hit_limit = true;
         return false;
+      }
+      if constexpr (kSeamVisits) {
+        if (seam) {  // false unless the caller compiled seam visits
+          // rows y - 1 .. y + 1 of every entry
+          uint32_t need = 0;
+          for (int e = lane(); e < n; e += 64) {
+            const int y = (s.q[0][e] & ~kRose) / TW;
+            need |= (uint32_t)((7ull << y) >> 1);
+          }
+          if (need) atomicOr(&s.need, need);
+          wsync();
+          need = __builtin_amdgcn_readfirstlane(s.need);
+          ensure_rows(s, im, y0, x0, kp, need & kAllRows);
+        }
       }
       vs.iters++;
       vs.pushes += n;
@@ -1183,6 +1360,7 @@ struct Tile {
   // fixed point, once its border raises a neighbour (sweep_rounds).
   // Inlined into each caller: the counters and the limit flag then stay in
   // registers instead of scratch memory.
+  template <bool SEAM = false>
   __device__ __forceinline__ static bool solve(L& s, int64_t y0, int64_t x0, int sweeps, bool seeded,
                                int seed_queue_max, uint32_t waves, uint32_t iter_limit,
                                VisitStats& vs, bool& hit_limit, uint32_t* watch,
@@ -1190,16 +1368,24 @@ struct Tile {
                                int sides, bool resume, bool early) {
     int budget = sweeps;
     int first_pass = 0;
+    // a seam visit (load_seam; only workers that make them compile SEAM) has
+    // staged only part of the tile
+    bool seam = false;
+    if constexpr (SEAM && kSeamVisits)
+      seam = __builtin_amdgcn_readfirstlane(s.loaded) != kAllRows;
     if (resume) {
       if (budget < 1) budget = 1;
     } else if (seeded) {
       const int n = halo_receivers(s, first_pass);
       if (n == 0) return false;
       if (n <= seed_queue_max) {
-        if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return false;
+        if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit, seam, im, y0, x0, kp))
+          return false;
       }
       if (budget < 1) budget = 1;
     }
+    // rounds of passes and scans read the whole tile
+    if (seam) ensure_all_rows(s, im, y0, x0, kp);
     for (uint32_t guard = 0;; ++guard) {
       const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, kp, t, tx, sides,
                                  early);
@@ -1207,7 +1393,8 @@ struct Tile {
       if (r == kEarly) return true;
       const int n = scan_receivers(s);
       if (n == 0) return false;
-      if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit)) return false;
+      if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit, false, im, y0, x0, kp))
+        return false;
       if (budget < 1) budget = 1;
       if (guard >= iter_limit) {
         hit_limit = true;
@@ -1280,7 +1467,7 @@ struct Tile {
 };
 
 template <typename T, int CONN, int TH>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_persistent(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_persistent(
     DevImage one, const DevImage* __restrict__ imgs,
                                                    KParams kp, DevCtl* ctl, int* queue,
                                                    uint32_t* state, uint8_t* visited) {
@@ -1291,7 +1478,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // tile's write-back (32-row int32 tiles; plain launches only, see
 // prefetch_worker).
 template <typename T, int CONN, int TH>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_persistent_pf(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_persistent_pf(
     DevImage one, const DevImage* __restrict__ imgs, KParams kp, DevCtl* ctl, int* queue,
     uint32_t* state, uint8_t* visited) {
   if constexpr (Tile<T, CONN, TH>::kPrefetch)
