@@ -237,15 +237,21 @@ int iwpp_autotune(const iwpp_image *img, int dtype, int conn, iwpp_stream_t stre
  * on the device (a serving loop built around the same kernels; it has no
  * counterpart in the paper).  A dispatcher thread admits pending requests in
  * arrival order while the device bytes they hold (marker, mask and their
- * share of tile state and queues) fit in `budget_bytes` and fewer than
- * `max_inflight` requests are unfinished.  The requests admitted together
- * form one batched persistent launch on a free slot of `streams` HIP
- * streams; launches on different slots overlap on the device, so requests
- * that arrive while others run start as soon as a slot and memory free up.
+ * tiles' share of the library workspace) fit in `budget_bytes` and fewer
+ * than `max_inflight` requests are unfinished.  The requests admitted
+ * together form one batched persistent launch on a free slot of `streams`
+ * HIP streams; launches on different slots overlap on the device, so
+ * requests that arrive while others run start as soon as a slot and memory
+ * free up.  create allocates each slot's workspace for the most tiles the
+ * budget admits at once (whole 64-column tiles: about 3% of the budget per
+ * slot for uint8), so the dispatch path allocates and frees nothing.
  *   submit: non-blocking.  The buffers are the caller's and must stay valid
- *           until the request is waited for.  If `marker_init` is not NULL it
- *           is a device image with the marker's shape and row pitch that is
- *           copied into the marker (on the launch stream) before the
+ *           until the request is waited for.  `stream` is the stream on
+ *           which the caller produced them (NULL: the null stream): the
+ *           request's work starts only after the work queued on it before
+ *           submit (an event recorded there).  If `marker_init` is not NULL
+ *           it is a device image with the marker's shape and row pitch that
+ *           is copied into the marker (on the launch stream) before the
  *           reconstruction.  Returns IWPP_E_BUDGET if the request alone
  *           exceeds the budget.
  *   wait:   blocks until the request finishes (timeout_us < 0: forever;
@@ -258,7 +264,7 @@ typedef struct iwpp_server iwpp_server;
 int iwpp_server_create(size_t budget_bytes, int dtype, int conn, int streams,
                        int max_inflight, iwpp_server **out);
 int iwpp_server_submit(iwpp_server *s, const iwpp_image *img, const void *marker_init,
-                       uint64_t *ticket);
+                       iwpp_stream_t stream, uint64_t *ticket);
 int iwpp_server_wait(iwpp_server *s, uint64_t ticket, int64_t timeout_us, double *latency_us);
 int iwpp_server_destroy(iwpp_server *s);
 

@@ -104,7 +104,7 @@ def _load():
         "iwpp_batch_destroy": ([vp], i32),
         "iwpp_autotune": ([P(Image), i32, i32, vp, P(Params)], i32),
         "iwpp_server_create": ([ctypes.c_size_t, i32, i32, i32, i32, P(vp)], i32),
-        "iwpp_server_submit": ([vp, P(Image), vp, P(ctypes.c_uint64)], i32),
+        "iwpp_server_submit": ([vp, P(Image), vp, vp, P(ctypes.c_uint64)], i32),
         "iwpp_server_wait": ([vp, ctypes.c_uint64, i64, P(ctypes.c_double)], i32),
         "iwpp_server_destroy": ([vp], i32),
         "iwpp_release_workspace": ([], i32),
@@ -377,9 +377,11 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, marker, mask, marker_init=None) -> int:
+    def submit(self, marker, mask, marker_init=None, stream=None) -> int:
         """Queue R_mask(marker) in place; if `marker_init` is given it is
-        copied into `marker` on the device first."""
+        copied into `marker` on the device first.  The work starts after what
+        was queued on `stream` (default: torch's current stream) before the
+        call, so buffers written there just before are ready."""
         im, _ = _image(marker, mask)
         init = None
         if marker_init is not None:
@@ -388,7 +390,8 @@ class Server:
                 raise ValueError("marker_init must match the marker's shape, pitch and dtype")
             init = marker_init.data_ptr()
         t = ctypes.c_uint64()
-        rc = _load().iwpp_server_submit(self._h, ctypes.byref(im), init, ctypes.byref(t))
+        rc = _load().iwpp_server_submit(self._h, ctypes.byref(im), init, _stream_handle(stream),
+                                        ctypes.byref(t))
         if rc != OK:
             raise IwppError(rc, "iwpp_server_submit")
         self._keep[t.value] = (marker, mask, marker_init)

@@ -37,6 +37,7 @@ double now_us() {
 struct Request {
   iwpp_image img{};
   const void* init = nullptr;  // optional pristine marker copied in first
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
   uint64_t ticket = 0;
   size_t bytes = 0;
   int64_t tiles = 0;
@@ -64,6 +65,8 @@ struct iwpp_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   int launch_error = IWPP_OK;
+  std::vector<hipEvent_t> events;  // free events for the requests' ready marks
+  int64_t slot_tiles = 0;          // tiles each slot's workspace holds (allocated at create)
 };
 
 namespace {
@@ -80,11 +83,22 @@ struct Slot {
 
 size_t elem_size(int dtype) { return dtype == IWPP_U8 ? 1 : 4; }
 
+int64_t request_tiles(const iwpp_image& im, int tile_h) {
+  return ((im.H + tile_h - 1) / tile_h) * ((im.W + kTileW - 1) / kTileW);
+}
+
+// Library workspace per tile of a launch: state word, first-visit flag, image
+// index, ring slot, packed side columns of I and J.
+size_t tile_bytes(int dtype, int tile_h) {
+  return 4 + 1 + 4 + 4 + (size_t)2 * 2 * tile_h * elem_size(dtype);
+}
+
+// Device bytes a request holds: its marker and mask (the caller's) and its
+// tiles' share of the slot workspace (allocated once, at create).
 size_t request_bytes(const iwpp_image& im, int dtype, int tile_h) {
   const int64_t ld = im.ld ? im.ld : im.W;
-  const int64_t tiles = ((im.H + tile_h - 1) / tile_h) * ((im.W + kTileW - 1) / kTileW);
-  // marker + mask + per-tile state, visit flag and queue slots
-  return (size_t)(2 * ((im.H - 1) * ld + im.W)) * elem_size(dtype) + (size_t)tiles * 16;
+  return (size_t)(2 * ((im.H - 1) * ld + im.W)) * elem_size(dtype) +
+         (size_t)request_tiles(im, tile_h) * tile_bytes(dtype, tile_h);
 }
 
 // Host callback behind a launch: record completion (no HIP calls here).
@@ -127,9 +141,19 @@ int launch_batch(iwpp_server* srv, Slot* s, std::vector<Request*>& batch) {
   int grid = 0;
   KParams kp{};
   int rc = plan_queues(srv->v, srv->rp, base, n, s->staging[0], &grid, &kp);
-  if (!rc) rc = s->buf.ensure(base, kp.qcap * (uint32_t)kp.nq, n, false);
+  if (rc) return rc;
+  // The workspace was sized at create for the most tiles the budget admits
+  // at once (admission keeps a batch within it), so nothing is allocated or
+  // freed here.  Only the queue rings of a request wider than about 65,000
+  // pixels could outgrow it; ensure() then grows them (and waits for the
+  // slot's stream).
+  rc = s->buf.ensure(base, kp.qcap * (uint32_t)kp.nq, n, false);
   if (!rc) rc = s->buf.ensure_cols_for(srv->v.dtype, srv->v.tile_h, base);
   if (rc) return rc;
+  // the requests' buffers are ready once the work queued before submit on
+  // the callers' streams has run
+  for (Request* r : batch)
+    if (r->ready && hipStreamWaitEvent(s->st, r->ready, 0) != hipSuccess) return IWPP_E_HIP;
   if (hipMemcpyAsync(s->buf.descs, s->staging, n * sizeof(DevImage), hipMemcpyHostToDevice,
                      s->st) != hipSuccess)
     return IWPP_E_HIP;
@@ -162,12 +186,15 @@ void dispatcher_main(iwpp_server* srv) {
     std::vector<Request*> batch;
     if (free_slot) {
       // continuous batching: everything that has arrived and fits goes now
+      int64_t tiles = 0;
       while (!srv->pending.empty() && srv->inflight < srv->max_inflight) {
         Request* r = srv->pending.front();
         if (srv->in_use + r->bytes > srv->budget) break;  // wait for memory (FIFO order)
+        if (tiles + r->tiles > srv->slot_tiles) break;    // the rest goes to the next launch
         srv->pending.pop_front();
         srv->in_use += r->bytes;
         srv->inflight++;
+        tiles += r->tiles;
         batch.push_back(r);
       }
     }
@@ -246,13 +273,41 @@ int iwpp_server_create(size_t budget_bytes, int dtype, int conn, int streams, in
     s->buf.stream_owner = s->st;
     srv->slots.push_back(s);
   }
+  // Each slot's workspace holds the most tiles the budget admits at once
+  // (requests of whole tiles: marker and mask bytes plus workspace per
+  // tile), allocated now so that no allocation or free (which would wait for
+  // the device) falls on the dispatch path.
+  const size_t full_tile = (size_t)2 * srv->rp.tile_h * kTileW * elem_size(dtype) +
+                           tile_bytes(dtype, srv->rp.tile_h);
+  srv->slot_tiles = (int64_t)(budget_bytes / full_tile);
+  if (srv->slot_tiles < 1024) srv->slot_tiles = 1024;
+  const int64_t ring = srv->slot_tiles + (int64_t)kMaxQueues * (srv->rp.grid + 64 + 4096);
+  for (Slot* s : srv->slots) {
+    if (ring >= (int64_t(1) << 31)) rc = IWPP_E_ARG;
+    if (!rc) rc = s->buf.ensure(srv->slot_tiles, (uint32_t)ring, max_inflight, false);
+    if (!rc) rc = s->buf.ensure_cols_for(dtype, srv->rp.tile_h, srv->slot_tiles);
+    if (!rc && hipHostMalloc(&s->staging, max_inflight * sizeof(DevImage), hipHostMallocDefault) !=
+                   hipSuccess)
+      rc = IWPP_E_NOMEM;
+    if (!rc) s->staging_cap = max_inflight;
+  }
+  if (rc) {
+    for (Slot* o : srv->slots) {
+      o->buf.release();
+      if (o->staging) (void)hipHostFree(o->staging);
+      (void)hipStreamDestroy(o->st);
+      delete o;
+    }
+    delete srv;
+    return rc;
+  }
   srv->dispatcher = std::thread(dispatcher_main, srv);
   *out = srv;
   return IWPP_OK;
 }
 
 int iwpp_server_submit(iwpp_server* srv, const iwpp_image* img, const void* marker_init,
-                       uint64_t* ticket) {
+                       iwpp_stream_t stream, uint64_t* ticket) {
   if (!srv || !ticket) return IWPP_E_ARG;
   int rc = check_image(img, srv->dtype);
   if (rc) return rc;
@@ -260,13 +315,32 @@ int iwpp_server_submit(iwpp_server* srv, const iwpp_image* img, const void* mark
   r->img = *img;
   r->init = marker_init;
   r->bytes = request_bytes(*img, srv->dtype, srv->rp.tile_h);
-  if (r->bytes > srv->budget) {
+  r->tiles = request_tiles(*img, srv->rp.tile_h);
+  if (r->bytes > srv->budget || r->tiles > srv->slot_tiles) {
     delete r;
     return IWPP_E_BUDGET;
+  }
+  {
+    std::lock_guard<std::mutex> g(srv->mu);
+    if (!srv->events.empty()) {
+      r->ready = srv->events.back();
+      srv->events.pop_back();
+    }
+  }
+  if (!r->ready && hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) {
+    delete r;
+    return IWPP_E_HIP;
+  }
+  // the request's work waits for what the caller queued on `stream` so far
+  if (hipEventRecord(r->ready, (hipStream_t)stream) != hipSuccess) {
+    (void)hipEventDestroy(r->ready);
+    delete r;
+    return IWPP_E_HIP;
   }
   r->t_submit = now_us();
   std::lock_guard<std::mutex> g(srv->mu);
   if (srv->stop) {
+    srv->events.push_back(r->ready);
     delete r;
     return IWPP_E_ARG;
   }
@@ -293,6 +367,7 @@ int iwpp_server_wait(iwpp_server* srv, uint64_t ticket, int64_t timeout_us, doub
   const int status = r->status;
   if (latency_us) *latency_us = r->t_done - r->t_submit;
   srv->all.erase(it);
+  if (r->ready) srv->events.push_back(r->ready);  // the launch that waited on it is over
   delete r;
   return status;
 }
@@ -317,7 +392,11 @@ int iwpp_server_destroy(iwpp_server* srv) {
     (void)hipStreamDestroy(s->st);
     delete s;
   }
-  for (auto& kv : srv->all) delete kv.second;
+  for (auto& kv : srv->all) {
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    delete kv.second;
+  }
+  for (hipEvent_t e : srv->events) (void)hipEventDestroy(e);
   delete srv;
   return IWPP_OK;
 }

@@ -189,6 +189,84 @@ def test_stats_report_work(iwpp):
     assert st["launches"] >= 2
 
 
+def maze(seed, cells=31, reps=2):
+    """A perfect maze (depth-first search on a cells x cells grid: 1-pixel
+    corridors at odd coordinates, 1-pixel walls), tiled reps x reps, as a
+    uint8 mask (corridors 200, walls 0) with the marker lit at one corner: a
+    front that must wind through every corridor."""
+    rng = np.random.default_rng(seed)
+    n = 2 * cells + 2
+    T = np.zeros((n, n), np.uint8)
+    seen = np.zeros((cells, cells), bool)
+    stack = [(0, 0)]
+    seen[0, 0] = True
+    T[1, 1] = 200
+    while stack:
+        cy, cx = stack[-1]
+        nb = [(cy + dy, cx + dx) for dy, dx in ((0, 1), (1, 0), (0, -1), (-1, 0))
+              if 0 <= cy + dy < cells and 0 <= cx + dx < cells and not seen[cy + dy, cx + dx]]
+        if not nb:
+            stack.pop()
+            continue
+        ny, nx = nb[rng.integers(len(nb))]
+        T[2 * cy + 1 + (ny - cy), 2 * cx + 1 + (nx - cx)] = 200
+        T[2 * ny + 1, 2 * nx + 1] = 200
+        seen[ny, nx] = True
+        stack.append((ny, nx))
+    I = np.tile(T, (reps, reps))
+    # open the tiles' shared borders here and there so the front crosses them
+    for k in range(1, reps):
+        I[k * n - 1: k * n + 1, 1::8] = 200
+        I[1::8, k * n - 1: k * n + 1] = 200
+    J = np.zeros_like(I)
+    J[1, 1] = 200
+    return np.ascontiguousarray(I), J
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_queue_carries_winding_fronts_with_uint8_defaults(iwpp, conn):
+    """A maze defeats the rounds of directional passes (each round follows a
+    front through a few turns only), so under the uint8 defaults (16 rounds,
+    then the seed scan and the tile queue) the queue carries what the rounds
+    leave; the result is exact."""
+    I, J = maze(5)
+    announce("maze %dx%d u8 defaults, %d-conn" % (I.shape + (conn,)))
+    got, st = run(iwpp, I, J, conn)
+    same(got, expect(I, J, conn), "maze")
+    announce("maze: %d pixels queued in %d waves, %d rounds"
+             % (st["pixels_queued"], st["queue_iterations"], st["sweep_rounds"]))
+    assert st["pixels_queued"] > 0 and st["queue_iterations"] > 0, st
+
+
+def test_queue_overflow_falls_back_to_passes(iwpp):
+    """Without scan rounds before the queue (sweeps -1), an int32 h-dome tile
+    queues more receivers than its LDS queue holds (an eighth of the tile):
+    every first visit overflows, falls back to rounds of passes, and the
+    result is exact."""
+    I, J = synth.c3_i32(H=300, W=330)
+    announce("queue overflow int32")
+    got, st = run(iwpp, I, J, 8, params={"sweeps": -1})
+    same(got, expect(I, J, 8), "overflow")
+    assert st["queue_overflows"] > 0, st
+
+
+def test_queue_wave_bound_hands_over_to_passes(iwpp):
+    """With queue_waves 1 a tile queue that still holds receivers after one
+    wave hands the tile to rounds of passes (and a new scan); without a bound
+    the queue alone carries the maze front.  Both are exact."""
+    I, J = maze(9)
+    announce("queue wave bound")
+    base = {"sweeps": -1, "seed_queue": 100000}
+    got_a, st_a = run(iwpp, I, J, 8, params=dict(base, queue_waves=-1))
+    got_b, st_b = run(iwpp, I, J, 8, params=dict(base, queue_waves=1))
+    want = expect(I, J, 8)
+    same(got_a, want, "unbounded waves")
+    same(got_b, want, "one wave")
+    assert st_a["queue_overflows"] == 0 and st_a["sweep_rounds"] == 0, st_a
+    assert st_b["sweep_rounds"] > 0, st_b
+    assert st_a["queue_iterations"] > st_b["queue_iterations"], (st_a, st_b)
+
+
 # ------------------------------------------------------------------ batched
 
 

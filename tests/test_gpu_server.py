@@ -143,3 +143,36 @@ def test_server_full_size_stream(iwpp):
         for kk, out, _ in outs:
             if kk == k:
                 np.testing.assert_array_equal(out.cpu().numpy(), want)
+
+
+def test_server_waits_for_the_callers_stream(iwpp):
+    """A marker and mask written on a stream just before submit (here behind
+    a long dummy computation on that stream) are what the request reads: the
+    request's work starts after the work queued on the submitting stream."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    pool = _pool(4, 700, 900, seed=21)
+    srv = iwpp.Server(8 << 30, "u8", 8, streams=2, max_inflight=16)
+    side = torch.cuda.Stream()
+    try:
+        outs = []
+        for I, J, _ in pool:
+            with torch.cuda.stream(side):
+                a = torch.randn(4096, 4096, device=dev)
+                for _ in range(8):  # keeps the stream busy for a while
+                    a = a @ a
+                    a = a / a.abs().max()
+                mask = torch.from_numpy(I).to(dev, non_blocking=True)
+                marker = torch.from_numpy(J).to(dev, non_blocking=True)
+                marker.add_(0)
+                t = srv.submit(marker, mask, stream=side)
+            outs.append((marker, mask, t))
+        for marker, mask, t in outs:
+            rc, _ = srv.wait(t)
+            assert rc == iwpp.OK
+        torch.cuda.synchronize()
+        for (I, J, _), (marker, _, _) in zip(pool, outs):
+            np.testing.assert_array_equal(marker.cpu().numpy(), _expect(I, J))
+    finally:
+        srv.close()
