@@ -1,4 +1,5 @@
-"""Register and scratch budget of the persistent tile workers (CPU only).
+"""Register budget, scratch use and memory coherence of the persistent tile
+workers (CPU only).
 
 The persistent kernels are sized for two wavefronts per SIMD (eight tiles per
 CU), which holds only while one wavefront needs at most 256 registers (VGPRs
@@ -7,6 +8,18 @@ kernel grows; the helper then becomes a call with a stack frame and the
 kernel's register count is reported as a max() over its callees.  This test
 compiles the device code to gfx950 assembly and checks every persistent
 kernel for all three.
+
+Tiles are handed from a workgroup on one XCD to a workgroup on another, each
+with its own L2, without any L2 write-back or invalidate: every access to
+memory that other workgroups write during a launch (the marker J, the packed
+side columns of J and I, tile states, flags, queues) is an agent-scope
+relaxed atomic, served coherently device-wide (`sc1` on gfx950), and only the
+mask I, which nothing writes, is read with plain loads.  Two checks hold the
+sources to that: a lint of the device sources (every subscript of a pointer
+into the marker or the packed columns sits inside `ld_coherent` /
+`st_coherent`; three planted plain accesses must be caught), and the compiled
+persistent kernels (every global store carries `sc1`, and no `buffer_wbl2` or
+`buffer_inv` appears).
 """
 from __future__ import annotations
 
@@ -19,6 +32,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1605_00930_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+DEVICE_SOURCES = ("iwpp_device.h", "iwpp_kernels.hip", "iwpp_edt.hip")
 
 
 def _asm(src, out):
@@ -29,7 +43,8 @@ def _asm(src, out):
 
 
 @pytest.fixture(scope="module")
-def resources(tmp_path_factory):
+def persistent_asm(tmp_path_factory):
+    """{kernel symbol: (resource fields, body lines)} of every persistent kernel."""
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not found")
     d = tmp_path_factory.mktemp("asm")
@@ -39,20 +54,31 @@ def resources(tmp_path_factory):
         jobs.append((out, _asm(src, out)))
     res = {}
     pat = re.compile(r"^\s*\.set\s+(\S*k_persistent\S*)\.(num_vgpr|num_agpr|private_seg_size),\s*(.+)$")
+    label = re.compile(r"^(_Z\S+):")
     for out, p in jobs:
         log = p.communicate()[0].decode(errors="replace")
         assert p.returncode == 0, log
+        cur = None
         for line in open(out):
             m = pat.match(line)
             if m:
-                res.setdefault(m.group(1), {})[m.group(2)] = m.group(3).strip()
+                res.setdefault(m.group(1), ({}, []))[0][m.group(2)] = m.group(3).strip()
+                continue
+            m = label.match(line)
+            if m:
+                cur = m.group(1) if "k_persistent" in m.group(1) else None
+                continue
+            if line.startswith("\t.end_amdgpu") or line.startswith(".Lfunc_end"):
+                cur = None
+            if cur:
+                res.setdefault(cur, ({}, []))[1].append(line.strip())
     assert res, "no persistent kernels found in the assembly"
     return res
 
 
-def test_persistent_kernels_fit_two_waves_per_simd(resources):
+def test_persistent_kernels_fit_two_waves_per_simd(persistent_asm):
     bad = []
-    for name, r in sorted(resources.items()):
+    for name, (r, _) in sorted(persistent_asm.items()):
         vals = {k: r.get(k, "") for k in ("num_vgpr", "num_agpr", "private_seg_size")}
         if not all(v.isdigit() for v in vals.values()):
             bad.append("%s calls out-of-line helpers: %s" % (name, vals))
@@ -61,3 +87,112 @@ def test_persistent_kernels_fit_two_waves_per_simd(resources):
         if p != 0 or v + a > 256:
             bad.append("%s: %d VGPR + %d AGPR, %d B scratch" % (name, v, a, p))
     assert not bad, "\n".join(bad)
+
+
+def test_persistent_kernels_store_coherently_without_l2_maintenance(persistent_asm):
+    bad = []
+    checked = 0
+    for name, (_, body) in sorted(persistent_asm.items()):
+        stores = [l for l in body if l.startswith("global_store")]
+        if not stores:
+            continue
+        checked += 1
+        plain = [l for l in stores if not re.search(r"\bsc1\b", l)]
+        if plain:
+            bad.append("%s: %d of %d global stores without sc1, e.g. %s"
+                       % (name, len(plain), len(stores), plain[0]))
+        maint = [l for l in body if l.startswith(("buffer_wbl2", "buffer_inv"))]
+        if maint:
+            bad.append("%s: L2 maintenance %s" % (name, maint[0]))
+        # the marker rows go out as stores, never through the scalar cache
+        if any(l.startswith(("s_store", "s_buffer_store")) for l in body):
+            bad.append("%s: scalar store" % name)
+    assert checked >= 10, "expected the u8, i32 and distance-transform workers"
+    assert not bad, "\n".join(bad)
+
+
+# ----------------------------------------------------------------- source lint
+
+_SHARED_BASES = r"(?:im\.J|kp\.colJ|kp\.colI)\b"
+
+
+def _strip_comments(text):
+    text = re.sub(r"/\*.*?\*/", lambda m: " " * len(m.group(0)), text, flags=re.S)
+    return re.sub(r"//[^\n]*", "", text)
+
+
+def _shared_pointer_names(code):
+    """Local pointers initialised from the marker or a packed column."""
+    names = set()
+    decl = re.compile(r"\b(?:const\s+)?gptr<[^;=]*?>\s+(\w+)\s*=\s*([^;]*);")
+    for m in decl.finditer(code):
+        if re.search(_SHARED_BASES, m.group(2)):
+            names.add(m.group(1))
+    return names
+
+
+def _inside_coherent_call(prefix):
+    """True if `prefix` (the text before an access) ends inside the pointer
+    argument of ld_coherent / st_coherent: only '&', '(' and pointer casts
+    may stand between the call and the access."""
+    p = prefix.rstrip()
+    while True:
+        q = re.sub(r"\(\s*(?:const\s+)?gptr<[^()]*?>\s*\)\s*$", "", p).rstrip()
+        q = re.sub(r"[&(]\s*$", "", q).rstrip()
+        if q == p:
+            break
+        p = q
+    return re.search(r"\b(?:ld|st)_coherent\s*$", p) is not None
+
+
+def lint_coherent_access(sources):
+    """Accesses to the marker or the packed side columns that are not
+    agent-scope atomics: a list of 'file:line: text' findings."""
+    found = []
+    for fname, text in sources.items():
+        code = _strip_comments(text)
+        names = _shared_pointer_names(code)
+        pats = [re.compile(r"\b%s\s*\[" % re.escape(n)) for n in names]
+        pats.append(re.compile(_SHARED_BASES + r"\s*\)\s*\["))  # ((gptr<T>)kp.colJ)[k]
+        pats.append(re.compile(_SHARED_BASES + r"\s*\["))       # kp.colJ[k]
+        # a pointer is never multiplied, so '*' before one is a dereference
+        derefs = [re.compile(r"\*\s*%s\b" % re.escape(n)) for n in names]
+        lines = code.split("\n")
+        for i, line in enumerate(lines, 1):
+            for pat in pats:
+                for m in pat.finditer(line):
+                    if not _inside_coherent_call(line[:m.start()]):
+                        found.append("%s:%d: %s" % (fname, i, line.strip()))
+            for pat in derefs:
+                if pat.search(line):
+                    found.append("%s:%d: %s" % (fname, i, line.strip()))
+            if names and re.search(r"\b(?:%s)\s*->" % "|".join(map(re.escape, names)), line):
+                found.append("%s:%d: %s" % (fname, i, line.strip()))
+    return sorted(set(found))
+
+
+def _read_sources():
+    return {f: open(os.path.join(CSRC, f)).read() for f in DEVICE_SOURCES}
+
+
+def test_marker_and_side_columns_are_accessed_coherently():
+    src = _read_sources()
+    code = _strip_comments(src["iwpp_kernels.hip"])
+    # the lint sees the pointers it has to police
+    assert {"gJ"} <= _shared_pointer_names(code)
+    assert "row" in _shared_pointer_names(code)
+    assert "gS" in _shared_pointer_names(_strip_comments(src["iwpp_edt.hip"]))
+    assert lint_coherent_access(src) == []
+
+
+@pytest.mark.parametrize("old,new", [
+    ("(int)ld_coherent(&gJ[gy * im.ld + gx])", "(int)gJ[gy * im.ld + gx]"),
+    ("st_coherent(row, w[q]);", "*row = w[q];"),
+    ("ld_coherent(&((gptr<const T>)kp.colI)[k])", "((gptr<const T>)kp.colI)[k]"),
+])
+def test_lint_catches_a_plain_access(old, new):
+    src = _read_sources()
+    assert old in src["iwpp_kernels.hip"], old
+    src["iwpp_kernels.hip"] = src["iwpp_kernels.hip"].replace(old, new, 1)
+    found = lint_coherent_access(src)
+    assert len(found) == 1 and new in found[0], found
