@@ -11,8 +11,11 @@ site) and never below the exact transform.  With 8-connectivity it must be
 no farther from the exact transform than the oracle is: at most twice the
 oracle's rate of pixels that miss the exact distance (plus 1e-4 of the
 image), by at most twice its largest miss.  With 4-connectivity the passes
-take other paths than the FIFO queue and miss more often; the bound there is
-5% of the pixels, by at most 1.5 px.
+carry a site along a column, then along a row, where the oracle's FIFO queue
+moves it in staircases, and they miss more often than the oracle; there the
+same bound is taken against a CPU model of the library's passes
+(tests/edt_pass_model.py: the tile rules in bulk-synchronous rounds), which
+misses as the passes do.
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ import pytest
 import oracle
 import synth
 from tests import refdefs
+from tests.edt_pass_model import edt_pass_model
 
 pytestmark = pytest.mark.gpu
 
@@ -109,9 +113,14 @@ def test_valid_and_close_to_oracle(iwpp, conn):
         else:
             # 4-connected sites travel along a column in one pass and along a
             # row in the next (L-shaped paths) where the FIFO queue moves them
-            # in staircases; more of them are blocked by competing sites
-            assert g_rate <= 0.05
-            assert g_err <= 1.5
+            # in staircases; more of them are blocked by competing sites, as
+            # in the model of the passes
+            _, model = edt_pass_model(img, conn)
+            m_rate = (model != ex).mean()
+            m_err = (np.sqrt(model) - np.sqrt(ex)).max()
+            announce("  pass model %.5f (max %.3f px)" % (m_rate, m_err))
+            assert g_rate <= 2 * m_rate + 1e-4
+            assert g_err <= max(2 * m_err, 0.1)
         assert st["tile_visits"] >= st["tiles"]
 
 
