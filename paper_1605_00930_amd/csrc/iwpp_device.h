@@ -66,6 +66,20 @@ __device__ __forceinline__ void drain_memory() {
 __device__ __forceinline__ void wsync() { __syncthreads(); }
 
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+// OR of v over the wavefront, as a scalar: an inclusive OR-scan within each
+// row of 16 lanes (row_shr 1, 2, 4, 8), then rows joined by the row
+// broadcasts of lane 15 (into rows 1 and 3) and lane 31 (into rows 2 and
+// 3), so that lane 63 holds the OR of all lanes.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
 __device__ __forceinline__ uint64_t now() { return wall_clock64(); }
@@ -474,9 +488,24 @@ static __device__ __forceinline__ void prefetch_ring_ticket(DevCtl* ctl, const K
   if (qs.pre == kNoTicket && qs.backlog && qs.fp_done) qs.pre = take_ticket(&ctl->head[q].v);
 }
 
+// Lane d < 9: the neighbour tile in direction d (3 x 3 grid index) of tile
+// (ty, tx) of image im if `act` asks for it, else -1 (every other lane -1).
+__device__ __forceinline__ int neighbour_request(const DevImage& im, int64_t ty, int64_t tx,
+                                                 uint32_t act) {
+  const int d = threadIdx.x;
+  int n = -1;
+  if (d < 9 && ((act >> d) & 1u)) {
+    const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
+    if (ny >= 0 && ny < im.tiles_y && nx >= 0 && nx < im.tiles_x)
+      n = (int)(im.tile_base + ny * im.tiles_x + nx);
+  }
+  return n;
+}
+
 // Publish the end of a visit of tile t (whole wavefront, once the tile's
-// marker write-back is complete).  Lanes 0..8 ask the neighbours in `act`
-// for a visit while lane 9 tries to release t (one round trip).  A release
+// marker write-back is complete).  Lanes 0..8 ask the neighbours they name
+// in `n` (neighbour_request) for a visit while lane 9 tries to release t
+// (one round trip).  A release
 // adds to the worker's credit (QState); the neighbours that were idle are
 // covered by that credit, and only what it does not cover is added to the
 // pending count, together with their queue reservations (a second round
@@ -488,17 +517,12 @@ static __device__ __forceinline__ void prefetch_ring_ticket(DevCtl* ctl, const K
 // neighbour asked for while it ran goes back on its queue instead of being
 // run again by this worker (it stays counted as pending, and its state word
 // keeps the request until the next owner takes it).
-static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
-                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
-                       WorkerStats& ws, uint32_t& credit, bool release = true,
-                       bool requeue = false) {
+static __device__ __forceinline__ int publish_requests(DevCtl* ctl, int* queue,
+                                                       const KParams& kp, uint32_t* state,
+                                                       int t, int n, int cls, WorkerStats& ws,
+                                                       uint32_t& credit, bool release,
+                                                       bool requeue) {
   const int d = threadIdx.x;
-  int n = -1;
-  if (d < 9 && ((act >> d) & 1u)) {
-    const int64_t ny = ty + d / 3 - 1, nx = tx + d % 3 - 1;
-    if (ny >= 0 && ny < im.tiles_y && nx >= 0 && nx < im.tiles_x)
-      n = (int)(im.tile_base + ny * im.tiles_x + nx);
-  }
   bool fresh = false;  // was idle: this wavefront enqueues it
   bool released = false;
   bool again = false;  // lane 9: t goes back on its queue
@@ -565,6 +589,15 @@ static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KPa
   return res;
 }
 
+// publish() for the requests of mask `act` of tile (ty, tx).
+static __device__ __forceinline__ int publish(DevCtl* ctl, int* queue, const KParams& kp, uint32_t* state, int t,
+                       const DevImage& im, int64_t ty, int64_t tx, uint32_t act, int cls,
+                       WorkerStats& ws, uint32_t& credit, bool release = true,
+                       bool requeue = false) {
+  return publish_requests(ctl, queue, kp, state, t, neighbour_request(im, ty, tx, act), cls, ws,
+                          credit, release, requeue);
+}
+
 // Geometry of tile t: its image and the origin of the tile in it.
 struct TilePos {
   DevImage im;
@@ -590,12 +623,15 @@ __device__ __forceinline__ TilePos tile_pos(const DevImage& one, const DevImage*
 
 // The persistent worker of a tile policy that prefetches (TP::kPrefetch):
 // while tile t is solved, the next first-pass ticket is taken and the next
-// tile's state word exchanged to running; once t is solved, the next tile's
-// loads are issued into registers, before t is written back, drained and
-// published, so their round trip overlaps those steps.  A tile that a
-// neighbour asks for while it runs goes back on its queue (the registers
-// already hold the next tile) instead of being run again in place.  Only
-// plain launches use it: no gray-level bands, no visit limit.
+// tile's state word exchanged to running; once t is solved, its activation
+// mask is taken and the next tile's loads are issued into registers before
+// t is written back, so their round trip overlaps the write-back.  t is
+// published only after the next tile's solve: by then its stores have
+// completed, and the drain before the publication costs nothing.  A tile
+// that a neighbour asks for while it runs (or waits for its publication)
+// goes back on its queue (the registers already hold the next tile) instead
+// of being run again in place.  Only plain launches use it: no gray-level
+// bands, no visit limit.
 template <typename TP>
 __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __restrict__ imgs,
                                                 const KParams& kp, DevCtl* ctl, int* queue,
@@ -628,6 +664,11 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
     bool seam = false;
     if constexpr (TP::kSeamVisits) seam = !(fv & 1) && kp.colJ;
     if (!seam) TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
+    // the tile written back before this one, awaiting its publication
+    // (dt < 0: none): its neighbour requests (lanes 0..8) and whether it was
+    // a first visit
+    int dt = -1, dn = -1;
+    bool dfirst = false;
     for (;;) {
       uint32_t c1 = (uint32_t)now();
       ws.t_idle += c1 - c0;
@@ -670,13 +711,23 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
                                           tp.im, kp, t, tp.tx, sides, false, false);
       uint32_t c3 = (uint32_t)now();
       ws.t_solve += c3 - c2;
+      // the previous tile: its write-back had this solve to complete (the
+      // drain also covers the exchange and flag reads of the next tile)
+      drain_memory();
+      if (dt >= 0) {
+        if (lead && dfirst) st_coherent(&visited[dt], (uint8_t)1);
+        publish_requests(ctl, queue, kp, state, dt, dn, 0, ws, qs.credit, true, true);
+      }
+      uint32_t c4 = (uint32_t)now();
+      ws.t_sync += c4 - c3;
+      // the activation mask reads the tile before its stores are issued
+      int amax = 0;
+      const uint32_t act = TP::activation_mask(s, tp.y0, tp.x0, false, amax);
       nx = __builtin_amdgcn_readfirstlane(nx);
       if (__builtin_amdgcn_readfirstlane(ended)) nx = -1;
       int nfv = 0;
       TilePos np = tp;
       if (nx >= 0) {
-        // the exchange is complete before the tile is read (as at a pop)
-        drain_memory();
         nfv = __builtin_amdgcn_readfirstlane((f0 == 0 ? 1 : 0) | (f1 ? 2 : 0) | (f2 ? 4 : 0));
         np = tile_pos<TH>(one, imgs, kp, nx);
         TP::issue(P, np.im, np.y0, np.x0, kp, nx, np.tx, nfv >> 1);
@@ -684,23 +735,28 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
         TP::clear_pre(P);
       }
       TP::store(s, tp.im, tp.y0, tp.x0, kp, t, first);
-      int amax = 0;
-      const uint32_t act = TP::activation_mask(s, tp.y0, tp.x0, false, amax);
-      uint32_t c4 = (uint32_t)now();
-      ws.t_store += c4 - c3;
+      const int n = neighbour_request(tp.im, tp.ty, tp.tx, act);
+      c0 = (uint32_t)now();
+      ws.t_store += c0 - c4;
       ws.add(vs);
       if (lead) {
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
-      // the write-back (and this tile's packed side columns) is complete
-      // before anyone is told about it
-      drain_memory();
-      if (lead && first) st_coherent(&visited[t], (uint8_t)1);
-      publish(ctl, queue, kp, state, t, tp.im, tp.ty, tp.tx, act, 0, ws, qs.credit, true, true);
-      c0 = (uint32_t)now();
-      ws.t_sync += c0 - c4;
-      if (nx < 0) break;
+      if (nx < 0) {
+        // no next tile: publish this one now (its write-back and packed
+        // side columns complete first)
+        drain_memory();
+        if (lead && first) st_coherent(&visited[t], (uint8_t)1);
+        publish_requests(ctl, queue, kp, state, t, n, 0, ws, qs.credit, true, true);
+        uint32_t c5 = (uint32_t)now();
+        ws.t_sync += c5 - c0;
+        c0 = c5;
+        break;
+      }
+      dt = t;
+      dn = n;
+      dfirst = first;
       t = nx;
       fv = nfv;
       tp = np;

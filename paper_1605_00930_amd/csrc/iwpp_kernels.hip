@@ -1155,7 +1155,10 @@ struct Tile {
   // y + 1 of J in registers (and, for lanes 0 and 63, the halo column beside
   // them, as in the passes); the columns beside come from the lanes beside.
   // A pixel's own value is part of the maximum, which changes nothing: the
-  // test is whether the maximum exceeds it.
+  // test is whether the maximum exceeds it.  Each lane collects its
+  // receivers as a bitmask over 32 rows; only the rows where some lane has
+  // one are then compacted (ballot + mbcnt, in row order), since after a
+  // round of passes most rows hold none.
   __device__ static int scan_receivers(L& s) {
     int n = 0;
     const int x = lane();
@@ -1163,6 +1166,8 @@ struct Tile {
     int ja = jv(s, -1, x), jb = jv(s, 0, x);
     int fa = jv(s, -1, fx), fb = jv(s, 0, fx);
     constexpr int R = 8;
+    static_assert(TH % 32 == 0, "receiver rows are gathered 32 at a time");
+    uint32_t bits = 0;  // bit y % 32: pixel (y, x) is a receiver
 #pragma unroll 1
     for (int yb = 0; yb < TH; yb += R) {
       int jn[R], fn[R], ii[R];
@@ -1172,7 +1177,6 @@ struct Tile {
         fn[k] = jv(s, yb + k + 1, fx);
         ii[k] = iv(s, yb + k, x);
       }
-      bool r[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) {
         int m;
@@ -1182,14 +1186,22 @@ struct Tile {
         } else {
           m = max_sides(imax(imax(ja, jn[k]), fb), jb);
         }
-        r[k] = jb < ii[k] && m > jb;
+        bits |= (uint32_t)(jb < ii[k] && m > jb) << ((yb & 31) + k);
         ja = jb;
         jb = jn[k];
         fa = fb;
         fb = fn[k];
       }
-#pragma unroll
-      for (int k = 0; k < R; ++k) push(s, 0, n, r[k], (yb + k) * TW + x);
+      // after each 32 rows: compact the rows that hold a receiver, in row
+      // order (most rows hold none)
+      if (((yb + R) & 31) == 0) {
+        const int g = (yb + R - 32) * TW + x;
+        for (uint32_t rows = wave_or(bits); rows; rows &= rows - 1) {
+          const int y = __builtin_ctz(rows);
+          push(s, 0, n, (bits >> y) & 1u, g + y * TW);
+        }
+        bits = 0;
+      }
     }
     wsync();
     return n;
@@ -1239,9 +1251,7 @@ struct Tile {
       }
       push(s, 0, n, r, y * TW + x);
     }
-    uint32_t all = 0;
-    for (int b = 0; b < 4; ++b)
-      if (__ballot((sides >> b) & 1u)) all |= 1u << b;
+    const uint32_t all = wave_or(sides);
     first_pass = all ? __builtin_ctz(all) : 0;
     wsync();
     return n;
@@ -1422,35 +1432,56 @@ struct Tile {
                                              int& amax) {
     uint32_t m = 0;
     int vmax = LO;
-    // border pixel (value j) against halo pixel (hy, hx)
-    auto check = [&](int j, int hy, int hx) {
-      const int jh = jv(s, hy, hx);
-      if (j > jh && jh < iv(s, hy, hx)) {
+    constexpr int ND = CONN == 8 ? 3 : 1;  // halo pixels beside a border pixel
+    // border pixel (value j, `changed` since the load) against halo pixel
+    // (hy, hx) of value jh and mask value ih
+    auto check = [&](bool changed, int j, int jh, int ih, int hy, int hx) {
+      if (changed && j > jh && jh < ih) {
         const int cy = hy < 0 ? 0 : (hy >= TH ? 2 : 1);
         const int cx = hx < 0 ? 0 : (hx >= TW ? 2 : 1);
         m |= 1u << (cy * 3 + cx);
         vmax = imax(vmax, j);
       }
     };
+    // every LDS read of a side is issued before the first test, so that they
+    // share one wait
     {
       const int x = lane();
       const int jt = jv(s, 0, x), jb = jv(s, TH - 1, x);
-      const bool ct = jt != (int)s.b_top[x], cb = jb != (int)s.b_bot[x];
+      const int bt = (int)s.b_top[x], bb = (int)s.b_bot[x];
+      int ht[ND], it[ND], hb[ND], ib[ND];
 #pragma unroll
-      for (int d = -1; d <= 1; ++d) {
-        if (CONN == 4 && d != 0) continue;
-        if (ct) check(jt, -1, x + d);
-        if (cb) check(jb, TH, x + d);
+      for (int k = 0; k < ND; ++k) {
+        const int d = ND == 3 ? k - 1 : 0;
+        ht[k] = jv(s, -1, x + d);
+        it[k] = iv(s, -1, x + d);
+        hb[k] = jv(s, TH, x + d);
+        ib[k] = iv(s, TH, x + d);
+      }
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        const int d = ND == 3 ? k - 1 : 0;
+        check(jt != bt, jt, ht[k], it[k], -1, x + d);
+        check(jb != bb, jb, hb[k], ib[k], TH, x + d);
       }
     }
     for (int y = lane(); y < TH; y += 64) {
       const int jl = jv(s, y, 0), jr = jv(s, y, TW - 1);
-      const bool cl = jl != (int)s.b_left[y], cr = jr != (int)s.b_right[y];
+      const int bl = (int)s.b_left[y], br = (int)s.b_right[y];
+      int hl[ND], il[ND], hr[ND], ir[ND];
 #pragma unroll
-      for (int d = -1; d <= 1; ++d) {
-        if (CONN == 4 && d != 0) continue;
-        if (cl) check(jl, y + d, -1);
-        if (cr) check(jr, y + d, TW);
+      for (int k = 0; k < ND; ++k) {
+        const int d = ND == 3 ? k - 1 : 0;
+        hl[k] = jv(s, y + d, -1);
+        il[k] = iv(s, y + d, -1);
+        hr[k] = jv(s, y + d, TW);
+        ir[k] = iv(s, y + d, TW);
+      }
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        const int d = ND == 3 ? k - 1 : 0;
+        check(jl != bl, jl, hl[k], il[k], y + d, -1);
+        check(jr != br, jr, hr[k], ir[k], y + d, TW);
       }
     }
     amax = LO;
@@ -1458,12 +1489,9 @@ struct Tile {
       for (int off = 32; off > 0; off >>= 1) vmax = imax(vmax, __shfl_xor(vmax, off));
       amax = __builtin_amdgcn_readfirstlane(vmax);
     }
-    // OR across the wavefront
-    uint32_t all = 0;
-    for (int d = 0; d < 9; ++d)
-      if (__ballot((m >> d) & 1u)) all |= 1u << d;
-    return all;
+    return wave_or(m);
   }
+
 };
 
 template <typename T, int CONN, int TH>
