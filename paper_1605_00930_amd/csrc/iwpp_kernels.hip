@@ -1220,17 +1220,24 @@ struct Tile {
     {
       const int x = lane();
       const int fx = x == 0 ? -1 : (x == TW - 1 ? TW : x);
+      // every read first, then the tests (one wait for all of them); lanes
+      // 0 and 63 also take the halo column beside them
+      int j[2], i[2], h[2], f[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int y = b == 0 ? 0 : TH - 1, hy = b == 0 ? -1 : TH, iy = b == 0 ? 1 : TH - 2;
-        const int j = jv(s, y, x);
-        int h = jv(s, hy, x);
-        if (CONN == 8) h = imax(h, imax(jv(s, hy, x - 1), jv(s, hy, x + 1)));
-        if (fx != x) {
-          h = imax(h, jv(s, y, fx));
-          if (CONN == 8) h = imax(h, jv(s, iy, fx));
-        }
-        const bool r = j < iv(s, y, x) && h > j;
+        j[b] = jv(s, y, x);
+        i[b] = iv(s, y, x);
+        h[b] = jv(s, hy, x);
+        if (CONN == 8) h[b] = imax(h[b], imax(jv(s, hy, x - 1), jv(s, hy, x + 1)));
+        f[b] = jv(s, y, fx);
+        if (CONN == 8) f[b] = imax(f[b], jv(s, iy, fx));
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int y = b == 0 ? 0 : TH - 1;
+        const int hh = fx != x ? imax(h[b], f[b]) : h[b];
+        const bool r = j[b] < i[b] && hh > j[b];
         if (r) sides |= (1u << b) | (x == 0 ? 4u : 0u) | (x == TW - 1 ? 8u : 0u);
         push(s, 0, n, r, y * TW + x);
       }
@@ -1241,14 +1248,13 @@ struct Tile {
       const bool right = e >= NS;
       const int y = 1 + (right ? e - NS : e);
       const int x = right ? TW - 1 : 0, hx = right ? TW : -1;
-      bool r = false;
-      if (e < 2 * NS) {
-        const int j = jv(s, y, x);
-        int h = jv(s, y, hx);
-        if (CONN == 8) h = imax(h, imax(jv(s, y - 1, hx), jv(s, y + 1, hx)));
-        r = j < iv(s, y, x) && h > j;
-        if (r) sides |= right ? 8u : 4u;
-      }
+      // lanes past the last entry read row 1 and take nothing
+      const int yr = e < 2 * NS ? y : 1;
+      const int j = jv(s, yr, x), i = iv(s, yr, x);
+      int h = jv(s, yr, hx);
+      if (CONN == 8) h = imax(h, imax(jv(s, yr - 1, hx), jv(s, yr + 1, hx)));
+      const bool r = e < 2 * NS && j < i && h > j;
+      if (r) sides |= right ? 8u : 4u;
       push(s, 0, n, r, y * TW + x);
     }
     const uint32_t all = wave_or(sides);

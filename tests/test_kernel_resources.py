@@ -122,13 +122,18 @@ def _strip_comments(text):
 
 
 def _shared_pointer_names(code):
-    """Local pointers initialised from the marker or a packed column."""
+    """Local pointers initialised from the marker or a packed column, or
+    from another such pointer."""
     names = set()
     decl = re.compile(r"\b(?:const\s+)?gptr<[^;=]*?>\s+(\w+)\s*=\s*([^;]*);")
-    for m in decl.finditer(code):
-        if re.search(_SHARED_BASES, m.group(2)):
-            names.add(m.group(1))
-    return names
+    decls = [(m.group(1), m.group(2)) for m in decl.finditer(code)]
+    while True:
+        known = [_SHARED_BASES] + [r"\b%s\b" % re.escape(n) for n in names]
+        pat = re.compile("|".join(known))
+        new = {n for n, init in decls if pat.search(init)} - names
+        if not new:
+            return names
+        names |= new
 
 
 def _inside_coherent_call(prefix):
@@ -179,8 +184,8 @@ def test_marker_and_side_columns_are_accessed_coherently():
     src = _read_sources()
     code = _strip_comments(src["iwpp_kernels.hip"])
     # the lint sees the pointers it has to police
-    assert {"gJ"} <= _shared_pointer_names(code)
-    assert "row" in _shared_pointer_names(code)
+    assert {"gJ", "row"} <= _shared_pointer_names(code)
+    assert "gI" not in _shared_pointer_names(code)  # the mask is read-only
     assert "gS" in _shared_pointer_names(_strip_comments(src["iwpp_edt.hip"]))
     assert lint_coherent_access(src) == []
 
@@ -196,3 +201,16 @@ def test_lint_catches_a_plain_access(old, new):
     src["iwpp_kernels.hip"] = src["iwpp_kernels.hip"].replace(old, new, 1)
     found = lint_coherent_access(src)
     assert len(found) == 1 and new in found[0], found
+
+
+def test_lint_follows_derived_pointers():
+    src = {"probe.hip": """
+      const gptr<const T> gJ = (gptr<const T>)im.J;
+      const gptr<const uint64_t> pj = (gptr<const uint64_t>)(gJ + gy * im.ld + gx);
+      const gptr<const T> gI = (gptr<const T>)im.I;
+      a = ld_coherent(&pj[0]);
+      b = gI[k];
+      c = pj[1];
+    """}
+    found = lint_coherent_access(src)
+    assert len(found) == 1 and "c = pj[1]" in found[0], found
