@@ -178,11 +178,11 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
 // are seldom neighbours (each would otherwise load the other's border before
 // it changes and ask for a re-visit), and every later group starts from
 // finished neighbours.
-__device__ __forceinline__ int64_t phase_tile(int64_t tx, int64_t ty, int64_t i) {
-  const int64_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
+__device__ __forceinline__ uint32_t phase_tile(uint32_t tx, uint32_t ty, uint32_t i) {
+  const uint32_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
   // the group sizes, compared one after the other (no indexed array: that
   // would live in scratch memory)
-  const int64_t n0 = ey * ex, n1 = ey * ox, n2 = oy * ex;
+  const uint32_t n0 = ey * ex, n1 = ey * ox, n2 = oy * ex;
   int p = 0;
   if (i >= n0) {
     i -= n0;
@@ -196,21 +196,23 @@ __device__ __forceinline__ int64_t phase_tile(int64_t tx, int64_t ty, int64_t i)
       }
     }
   }
-  const int64_t w = (p & 1) ? ox : ex;
+  const uint32_t w = (p & 1) ? ox : ex;
   return (2 * (i / w) + (p >> 1)) * tx + 2 * (i % w) + (p & 1);
 }
 
 __device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, const DevImage* imgs,
                                                    int q, int64_t i) {
   if (kp.list_mode) return kp.list_in[i * kp.nq + q];
-  const int64_t c = (i / kp.chunk) * kp.nq + q;
-  const int64_t t = c * kp.chunk + i % kp.chunk;
-  if (kp.phase_tx > 0) return phase_tile(kp.phase_tx, kp.phase_ty, t);
+  const uint32_t ii = (uint32_t)i, ch = (uint32_t)kp.chunk;
+  const uint32_t c = (ii / ch) * (uint32_t)kp.nq + (uint32_t)q;
+  const uint32_t t = c * ch + ii % ch;
+  if (kp.phase_tx > 0) return phase_tile((uint32_t)kp.phase_tx, (uint32_t)kp.phase_ty, t);
   if (kp.phase_tx < 0) {
     // a batch: the pass covers the images one after the other (tile ids),
     // each in its own four phases
     const DevImage& im = imgs[kp.tile_img[t]];
-    return im.tile_base + phase_tile(im.tiles_x, im.tiles_y, t - im.tile_base);
+    return im.tile_base + phase_tile((uint32_t)im.tiles_x, (uint32_t)im.tiles_y,
+                                     t - (uint32_t)im.tile_base);
   }
   if (kp.order_mul == 1 && kp.order_add == 0) return t;
   return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);
@@ -323,7 +325,7 @@ __device__ __forceinline__ int64_t next_first_pass(DevCtl* ctl, int q, int64_t l
     if (qs.fp_done) return -1;
     const uint32_t h = qs.fp_pre != kNoTicket ? qs.fp_pre : take_ticket(&ctl->fphead[q].v);
     qs.fp_pre = kNoTicket;
-    const int64_t m = qs.fp_step;
+    const uint32_t m = qs.fp_step;
     const int64_t a = (int64_t)(h / m) * m * kFpChunk + h % m;
     if (a >= len) {
       qs.fp_done = true;
@@ -335,9 +337,16 @@ __device__ __forceinline__ int64_t next_first_pass(DevCtl* ctl, int q, int64_t l
   const int64_t pos = qs.fp_next;
   qs.fp_next += qs.fp_step;
   qs.fp_left--;
-  if ((qs.fp_left == 0 || qs.fp_next >= len) && qs.fp_pre == kNoTicket)
-    qs.fp_pre = take_ticket(&ctl->fphead[q].v);
   return pos;
+}
+
+// Lane 0, after next_first_pass: once this worker's chunk is used up, the
+// ticket of its next chunk is taken ahead (its round trip then overlaps a
+// visit).  A separate step, so that callers can issue it after the
+// arithmetic that maps the position to a tile.
+__device__ __forceinline__ void refill_first_pass(DevCtl* ctl, int q, int64_t len, QState& qs) {
+  if ((qs.fp_left == 0 || qs.fp_next >= len) && qs.fp_pre == kNoTicket && !qs.fp_done)
+    qs.fp_pre = take_ticket(&ctl->fphead[q].v);
 }
 
 // Lane 0: the next tile of queue q for this worker, -1 when the launch is
@@ -362,6 +371,7 @@ static __device__ __forceinline__ int take_tile(DevCtl* ctl, int* queue, const K
   if (pos >= 0) {
     first_pass = ready = true;
     v = (int)first_pass_tile(kp, imgs, q, pos);
+    refill_first_pass(ctl, q, len, qs);
   } else {
     uint32_t h = qs.pre;
     qs.pre = kNoTicket;
@@ -645,6 +655,38 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
   typename TP::Pre P;
   QState qs = init_qstate(kp, grid);
   const int64_t fp_len = first_pass_len(kp, q);
+  // Lead: the tile after the next one, if this worker's share of the first
+  // pass has one (-1 otherwise): its state word goes pending -> running and
+  // its flags are read now, and the results are used after the next solve.
+  // Taken right after the drain that follows a solve, when no memory
+  // operation is outstanding, so that nothing in here waits for one; its
+  // round trip overlaps the publication that follows.
+  int nx = -1;
+  uint8_t f0 = 0, f1 = 0, f2 = 0;
+  uint32_t ended = 0;  // the launch was stopped (an abort): take no next tile
+  auto take_next = [&]() {
+    nx = -1;
+    f0 = f1 = f2 = 0;
+    ended = 0;
+    if (lead) {
+      // the arithmetic first, then the memory operations
+      const int64_t pos = qs.pre == kNoTicket ? next_first_pass(ctl, q, fp_len, qs) : -1;
+      if (pos >= 0) nx = (int)first_pass_tile(kp, imgs, q, pos);
+      ended = ld_rlx_u32(&ctl->done.v);
+      if (pos >= 0) {
+        refill_first_pass(ctl, q, fp_len, qs);
+        __hip_atomic_exchange(&state[nx], TS_RUNNING, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        f0 = ld_coherent(&visited[nx]);
+        if (kp.colJ) {
+          if (nx > 0) f1 = ld_coherent(&visited[nx - 1]);
+          if (nx + 1 < kp.ntiles) f2 = ld_coherent(&visited[nx + 1]);
+        }
+      } else {
+        prefetch_ring_ticket(ctl, kp, q, qs);
+      }
+    }
+  };
   // Outer loop: take a tile the plain way (this worker's share of the first
   // pass is done, or a ring ticket was taken ahead); its visit loads it.
   // Inner loop: visit it; while the first pass has a next position for this
@@ -664,6 +706,7 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
     bool seam = false;
     if constexpr (TP::kSeamVisits) seam = !(fv & 1) && kp.colJ;
     if (!seam) TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
+    take_next();  // the tile after t
     // the tile written back before this one, awaiting its publication
     // (dt < 0: none): its neighbour requests (lanes 0..8) and whether it was
     // a first visit
@@ -682,28 +725,6 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
         viol = TP::commit(s, P, first, kp);
       uint32_t c2 = (uint32_t)now();
       ws.t_load += c2 - c1;
-      // the next tile, if this worker's share of the first pass has one: its
-      // state word (pending -> running) and its flags are taken now, and the
-      // round trip overlaps the solve
-      int nx = -1;
-      uint8_t f0 = 0, f1 = 0, f2 = 0;
-      uint32_t ended = 0;  // the launch was stopped (an abort): take no next tile
-      if (lead) {
-        ended = ld_rlx_u32(&ctl->done.v);
-        const int64_t pos = qs.pre == kNoTicket ? next_first_pass(ctl, q, fp_len, qs) : -1;
-        if (pos >= 0) {
-          nx = (int)first_pass_tile(kp, imgs, q, pos);
-          __hip_atomic_exchange(&state[nx], TS_RUNNING, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
-          f0 = ld_coherent(&visited[nx]);
-          if (kp.colJ) {
-            if (nx > 0) f1 = ld_coherent(&visited[nx - 1]);
-            if (nx + 1 < kp.ntiles) f2 = ld_coherent(&visited[nx + 1]);
-          }
-        } else {
-          prefetch_ring_ticket(ctl, kp, q, qs);
-        }
-      }
       VisitStats vs;
       bool hit = false;
       TP::template solve<TP::kSeamVisits>(s, tp.y0, tp.x0, kp.sweeps, !first, kp.seed_queue_max,
@@ -711,9 +732,17 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
                                           tp.im, kp, t, tp.tx, sides, false, false);
       uint32_t c3 = (uint32_t)now();
       ws.t_solve += c3 - c2;
-      // the previous tile: its write-back had this solve to complete (the
-      // drain also covers the exchange and flag reads of the next tile)
+      // the previous tile's write-back had this solve to complete, and the
+      // next tile's exchange and flag reads are complete before its loads
+      // are issued (as at a pop)
       drain_memory();
+      int nt = __builtin_amdgcn_readfirstlane(nx);
+      if (__builtin_amdgcn_readfirstlane(ended)) nt = -1;
+      int nfv = 0;
+      if (nt >= 0) {
+        nfv = __builtin_amdgcn_readfirstlane((f0 == 0 ? 1 : 0) | (f1 ? 2 : 0) | (f2 ? 4 : 0));
+        take_next();  // the tile after nt
+      }
       if (dt >= 0) {
         if (lead && dfirst) st_coherent(&visited[dt], (uint8_t)1);
         publish_requests(ctl, queue, kp, state, dt, dn, 0, ws, qs.credit, true, true);
@@ -723,14 +752,10 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       // the activation mask reads the tile before its stores are issued
       int amax = 0;
       const uint32_t act = TP::activation_mask(s, tp.y0, tp.x0, false, amax);
-      nx = __builtin_amdgcn_readfirstlane(nx);
-      if (__builtin_amdgcn_readfirstlane(ended)) nx = -1;
-      int nfv = 0;
       TilePos np = tp;
-      if (nx >= 0) {
-        nfv = __builtin_amdgcn_readfirstlane((f0 == 0 ? 1 : 0) | (f1 ? 2 : 0) | (f2 ? 4 : 0));
-        np = tile_pos<TH>(one, imgs, kp, nx);
-        TP::issue(P, np.im, np.y0, np.x0, kp, nx, np.tx, nfv >> 1);
+      if (nt >= 0) {
+        np = tile_pos<TH>(one, imgs, kp, nt);
+        TP::issue(P, np.im, np.y0, np.x0, kp, nt, np.tx, nfv >> 1);
       } else {
         TP::clear_pre(P);
       }
@@ -743,7 +768,7 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
-      if (nx < 0) {
+      if (nt < 0) {
         // no next tile: publish this one now (its write-back and packed
         // side columns complete first)
         drain_memory();
@@ -757,7 +782,7 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       dt = t;
       dn = n;
       dfirst = first;
-      t = nx;
+      t = nt;
       fv = nfv;
       tp = np;
       seam = false;
