@@ -87,6 +87,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def persistent_kernel_name(dtype: str, params: dict, mode: int) -> str:
+    """The persistent kernel a single-image call launches: 32-row int32 tiles
+    (the int32 default) in the plain persistent mode run the worker that
+    prefetches the next tile."""
+    tile_h = params.get("tile_h") or (32 if dtype == "i32" else 64)
+    if dtype == "i32" and tile_h == 32 and not mode and not params.get("max_tile_visits"):
+        return "k_persistent_pf (tile worker, next-tile prefetch)"
+    return "k_persistent (tile worker)"
+
+
 def load_traffic(workload: str):
     """HBM bytes per launch from profiles/traffic_k_persistent_<workload>.txt, or None if the
     summary is missing or was taken on a different kernel source."""
@@ -409,7 +419,8 @@ def bench_single(args, torch, iwpp, workload=None, steps=None, warmup=None, quie
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_persistent (tile worker)", "kernel_ms": round(kms, 4),
+                     "kernel": persistent_kernel_name(dt, params, params.get("mode", 0)),
+                     "kernel_ms": round(kms, 4),
                      "algorithmic_bytes_per_launch": 3 * es * px},
         "parity": parity,
         "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
@@ -675,8 +686,9 @@ def main():
                          "reported under 'also' (auto: c2,c3u8 when the main workload is the "
                          "default c3i32 dilation; none: skip)")
     ap.add_argument("--also-steps", dest="also_steps", type=int, default=10)
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run the library copy kernel on this many MiB (profiler scaling)")
+    ap.add_argument("--calib-copy-mib", default="",
+                    help="comma-separated sizes in MiB: run the library copy kernel on each "
+                         "(the known-size reference that scales the profiler's byte counters)")
     args = ap.parse_args()
     if args.op != "dilate" and args.workload in ("c4", "c5", "edt", "edt32k"):
         ap.error("--op applies to single-image workloads only")
@@ -698,8 +710,8 @@ def main():
         __graft_entry__.build()
     iwpp._load()
 
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib << 20
+    for mib in [int(m) for m in args.calib_copy_mib.split(",") if m]:
+        n = mib << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
         a.fill_(1)
