@@ -11,7 +11,7 @@ import pytest
 
 import bench
 
-WORKLOADS = ("c2", "c3i32", "c3u8")
+WORKLOADS = ("c2", "c3i32", "c3u8", "c4")
 
 
 def summary_fields(workload):
@@ -43,12 +43,31 @@ def test_traffic_summary_is_consistent(workload):
     assert float(kv["traffic_over_algorithmic"]) == pytest.approx((fetch + write) / algo,
                                                                   abs=1e-3)
     # the workload's algorithmic bytes: read I and J, write R, sizeof(T) each
-    side = 4096 if workload == "c2" else 32768
-    per_px = 12 if workload == "c3i32" else 3
-    assert algo == per_px * side * side
-    # every dispatch listed contributes; the calibration scale turns KiB into bytes
-    kib = [float(x) for x in kv["k_persistent_fetch_kib_per_dispatch"].split(",")]
+    if workload == "c4":
+        assert algo > 0  # 256 images of uneven size
+    else:
+        side = 4096 if workload == "c2" else 32768
+        per_px = 12 if workload == "c3i32" else 3
+        assert algo == per_px * side * side
+    # the calibration scale turns the counters' KiB into bytes
+    kib = [float(x) for x in kv["worker_fetch_kib_per_dispatch"].split(",")]
     assert min(kib) > 0
+    assert fetch == pytest.approx(sum(kib) / len(kib) * 1024 / float(kv["scale_fetch"]), rel=1e-3)
+    wkib = [float(x) for x in kv["worker_write_kib_per_dispatch"].split(",")]
+    assert write == pytest.approx(sum(wkib) / len(wkib) * 1024 / float(kv["scale_write"]),
+                                  rel=1e-3)
+
+
+@pytest.mark.parametrize("workload", WORKLOADS)
+def test_counter_scale_does_not_depend_on_the_copy_size(workload):
+    # the copy of 64 MiB stays inside the 256 MB Infinity Cache, the copy of
+    # 1024 MiB does not; the counters read the same fraction of the true bytes
+    lines = open(os.path.join(bench.ROOT, "profiles",
+                              "traffic_k_persistent_%s.txt" % workload)).read().splitlines()
+    ratios = [l.split("counter/true")[1].split("/") for l in lines if "counter/true" in l]
+    assert len(ratios) == 4
+    for a, b in ratios:
+        assert float(a) == pytest.approx(float(b), rel=0.01)
 
 
 def test_traffic_missing_summary_is_none():
