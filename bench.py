@@ -423,10 +423,12 @@ def bench_single(args, torch, iwpp, workload=None, steps=None, warmup=None, quie
                      "kernel_ms": round(kms, 4),
                      "algorithmic_bytes_per_launch": 3 * es * px},
         "parity": parity,
-        "step_stats": {k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
-                                             "pixels_queued", "queue_overflows", "reprocessed",
-                                             "queue_iterations", "idle_ms", "load_ms", "solve_ms",
-                                             "store_ms", "sync_ms")},
+        "step_stats": dict({k: stats[k] for k in ("tiles", "tile_visits", "sweep_rounds",
+                                                  "pixels_queued", "queue_overflows",
+                                                  "reprocessed", "requeued", "launches",
+                                                  "queue_iterations", "idle_ms", "load_ms",
+                                                  "solve_ms", "store_ms", "sync_ms")},
+                           visits_per_tile=round(stats["tile_visits"] / stats["tiles"], 3)),
         "ms_min": round(float(np.min(call_ms)), 4), "ms_cv": round(float(np.std(call_ms) / ms), 4),
         "cv_protocol": cv_protocol(call_ms),
         "wall_ms_per_step_incl_restore": round(wall * 1e3 / steps, 4),
