@@ -631,17 +631,18 @@ __device__ __forceinline__ TilePos tile_pos(const DevImage& one, const DevImage*
   return p;
 }
 
-// The persistent worker of a tile policy that prefetches (TP::kPrefetch):
-// while tile t is solved, the next first-pass ticket is taken and the next
-// tile's state word exchanged to running; once t is solved, its activation
-// mask is taken and the next tile's loads are issued into registers before
-// t is written back, so their round trip overlaps the write-back.  t is
-// published only after the next tile's solve: by then its stores have
-// completed, and the drain before the publication costs nothing.  A tile
-// that a neighbour asks for while it runs (or waits for its publication)
-// goes back on its queue (the registers already hold the next tile) instead
-// of being run again in place.  Only plain launches use it: no gray-level
-// bands, no visit limit.
+// The persistent worker of a tile policy that prefetches (TP::kPrefetch).
+// Along its share of the first pass a worker keeps three tiles in flight:
+// the tile t it solves; the next tile n, whose loads it issues into
+// registers once t is solved and its activation mask taken, before t is
+// written back, so that their round trip overlaps the write-back; and the
+// tile after n, whose state word goes pending -> running (its flags read in
+// the same round trip) right after t's solve.  t is published only after
+// n's solve: by then its stores have completed, and the drain before the
+// publication costs nothing.  A tile that a neighbour asks for while it
+// runs (or waits for its publication) goes back on its queue (the registers
+// already hold the next tile) instead of being run again in place.  Only
+// plain launches use it: no gray-level bands, no visit limit.
 template <typename TP>
 __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __restrict__ imgs,
                                                 const KParams& kp, DevCtl* ctl, int* queue,
@@ -659,8 +660,10 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
   // pass has one (-1 otherwise): its state word goes pending -> running and
   // its flags are read now, and the results are used after the next solve.
   // Taken right after the drain that follows a solve, when no memory
-  // operation is outstanding, so that nothing in here waits for one; its
-  // round trip overlaps the publication that follows.
+  // operation is outstanding, so that nothing in here waits for one (a
+  // register hazard in its index arithmetic would otherwise wait for all of
+  // them); its round trip overlaps the publication that follows.  The first
+  // call of a run is made once that run's first tile has been issued.
   int nx = -1;
   uint8_t f0 = 0, f1 = 0, f2 = 0;
   uint32_t ended = 0;  // the launch was stopped (an abort): take no next tile
