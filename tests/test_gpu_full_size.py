@@ -9,10 +9,11 @@ tests/golden/full_size_sha256.txt by tests/golden/make_full_size_hashes.py
 digests are checked first, so a drift of the generators cannot pass as a
 parity failure or hide one.
 
+The served stream's whole request pool goes through the server the same way.
 On a mismatch the tests locate the difference for the report (diagnostics
 only, never the pass criterion): the int32 image against the oracle run on
 the spot, the uint8 image through properties and sampled single-pixel oracle
-searches, a batch image against the oracle.
+searches, a batch image or a request against the oracle.
 """
 from __future__ import annotations
 
@@ -198,3 +199,40 @@ def test_c1_c2_full_size_digests(iwpp):
         Jt = torch.from_numpy(J).to(dev)
         iwpp.reconstruct(Jt, torch.from_numpy(I).to(dev), 8)
         assert synth.sha256(Jt.cpu().numpy()) == g[name]["R"], name
+
+
+def test_c5_recipe_pool_through_the_server_digests(iwpp):
+    """The served stream's full request pool (256 requests, sides log-uniform
+    256..8192, h-dome and fill-holes markers), each submitted once in a
+    shuffled order to a server set up as bench.py sets it up (64 GB budget,
+    two launch slots, up to 64 in flight): every output against the stored
+    digest of the oracle's result for its request."""
+    import torch
+
+    g = golden()
+    announce("c5 pool of 256: generating")
+    pool = synth.c5_pool()
+    for k, (I, J, _) in enumerate(pool):
+        _check_inputs(g, "c5/%d" % k, I, J)
+    dev = torch.device("cuda:0")
+    masks = [torch.from_numpy(I).to(dev) for I, J, _ in pool]
+    markers = [torch.from_numpy(J).to(dev) for I, J, _ in pool]
+    order = [int(k) for k in np.random.default_rng(13).permutation(len(pool))]
+    announce("c5 pool of 256: submitting")
+    srv = iwpp.Server(64 << 30, "u8", 8, streams=2, max_inflight=64)
+    try:
+        tickets = [(k, srv.submit(markers[k], masks[k])) for k in order]
+        for k, t in tickets:
+            rc, lat = srv.wait(t)
+            assert rc == iwpp.OK and lat > 0, (k, rc)
+    finally:
+        srv.close()
+    announce("c5 pool of 256: comparing digests")
+    bad = [k for k in range(len(pool))
+           if synth.sha256(markers[k].cpu().numpy()) != g["c5/%d" % k]["R"]]
+    if bad:
+        I, J, _ = pool[bad[0]]
+        rc, R = oracle.reconstruct(J, I, 8)
+        assert rc == oracle.OK
+        raise AssertionError("%d requests differ (%s); request %d: %s" % (
+            len(bad), bad[:8], bad[0], _first_difference(markers[bad[0]].cpu().numpy(), R)))
