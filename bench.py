@@ -133,7 +133,8 @@ def golden():
 
 
 def host_cores() -> int:
-    """Host threads for the pooled CPU baselines: the box's share for one GPU."""
+    """Host threads for the pooled CPU baselines: the ones this process may
+    run on, at most 16 (a one-GPU share of a host that serves several GPUs)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
