@@ -133,8 +133,11 @@ typedef struct iwpp_stats {
  *   grid          persistent workgroups (0 = fill the device).
  *   max_tile_visits  stop after this many tile visits (0 = no limit); used to
  *                 test restart: the call then returns IWPP_E_INCOMPLETE.
- *   order_seed    0: tiles start in raster order; otherwise a seeded
- *                 permutation (results must not depend on it).
+ *   order_seed    0: the first visits go in four groups of tiles of
+ *                 alternate rows and columns (no two tiles of a group
+ *                 touch), in the order `first_pass` picks; otherwise a
+ *                 seeded permutation of the tiles (results must not depend
+ *                 on it).
  *   timing        non-zero: bracket the reconstruction kernels with HIP
  *                 events on the call's stream; iwpp_stats.kernel_ms then
  *                 reports their device time.
@@ -146,6 +149,17 @@ typedef struct iwpp_stats {
  *                 waves hands the tile to rounds of directional passes and a
  *                 new scan (0 = default 4, -1 = no limit).
  *   bands         mode 2: number of gray-level classes (0 = default 16).
+ *   first_pass    order of the four groups of first visits (order_seed 0):
+ *                 1 by rows of the group grid -- (even row, even column),
+ *                 (even, odd), (odd, even), (odd, odd) -- so that the second
+ *                 group already starts beside finished tiles, which suits
+ *                 fronts that travel from tile to tile (fill-holes); 2 the
+ *                 two diagonal groups first -- (even, even), (odd, odd),
+ *                 then (even, odd) and (odd, even) -- so that half the tiles
+ *                 start with all four edge neighbours finished and few need
+ *                 a re-visit, which suits fronts that stay local (h-domes).
+ *                 0 = default: 1 for uint8, 2 for int32 and the distance
+ *                 transform.  Results do not depend on it.
  */
 typedef struct iwpp_params {
   int32_t tile_h;
@@ -159,6 +173,7 @@ typedef struct iwpp_params {
   int32_t seed_queue;
   int32_t queue_waves;
   int32_t bands;
+  int32_t first_pass;
 } iwpp_params;
 
 /* Library version, e.g. 10000 for 1.0.0. */

@@ -71,7 +71,7 @@ class Params(ctypes.Structure):
                 ("max_tile_visits", ctypes.c_int64), ("order_seed", ctypes.c_uint32),
                 ("spin_limit", ctypes.c_uint32), ("timing", ctypes.c_int32),
                 ("seed_queue", ctypes.c_int32), ("queue_waves", ctypes.c_int32),
-                ("bands", ctypes.c_int32)]
+                ("bands", ctypes.c_int32), ("first_pass", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

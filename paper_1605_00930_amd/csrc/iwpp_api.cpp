@@ -119,6 +119,11 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   // straight to rounds of passes; int32 (h-dome): short fronts, few seeds
   base.seed_queue = dtype == IWPP_U8 ? -1 : 8;
   base.queue_waves = 4;
+  // uint8 (fill-holes): fronts travel in from the frame, so the second group
+  // of first visits should start beside finished tiles; int32 (h-domes):
+  // fronts stay local, and the diagonal groups first leave half the tiles
+  // with every edge neighbour finished
+  base.first_pass = dtype == IWPP_U8 ? 1 : 2;
   if (tuned) {
     std::lock_guard<std::mutex> g(g_mu);
     load_tune_cache_locked();
@@ -141,6 +146,7 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
   r.timing = 0;
   r.seed_queue_max = base.seed_queue < 0 ? 0 : base.seed_queue;
   r.bands = 16;
+  r.first_pass = base.first_pass;
   r.queue_waves = base.queue_waves < 0 ? UINT32_MAX : (uint32_t)base.queue_waves;
   if (user) {
     r.timing = user->timing;
@@ -148,6 +154,7 @@ Resolved resolve_params(const iwpp_params* user, int dtype, int conn, int64_t H,
     if (user->queue_waves)
       r.queue_waves = user->queue_waves < 0 ? UINT32_MAX : (uint32_t)user->queue_waves;
     if (user->bands) r.bands = user->bands;
+    if (user->first_pass) r.first_pass = user->first_pass;
     if (user->tile_h) r.tile_h = user->tile_h;
     if (user->sweeps) r.sweeps = user->sweeps < 0 ? 0 : user->sweeps;
     if (user->mode) r.mode = user->mode;
@@ -166,6 +173,7 @@ int check_params(const iwpp_params* p) {
   if (p->sweeps < -1 || p->sweeps > 64) return IWPP_E_ARG;
   if (p->mode < 0 || p->mode > 2) return IWPP_E_ARG;
   if (p->bands < 0 || p->bands > 4096) return IWPP_E_ARG;
+  if (p->first_pass < 0 || p->first_pass > 2) return IWPP_E_ARG;
   if (p->grid < 0 || p->max_tile_visits < 0) return IWPP_E_ARG;
   return IWPP_OK;
 }
@@ -536,6 +544,7 @@ int enqueue(Buffers& b, const Variant& v, const Resolved& rp, const DevImage& on
       kp.phase_tx = one.tiles_x;
       kp.phase_ty = one.tiles_y;
     }
+    kp.phase_diag = rp.first_pass == 2;
     rc = setup_cols(b, v, ntiles, kp);
     if (rc) return rc;
     HIP_TRY(launch_init(kp, b.ctl, b.queue, b.state, b.visited, nullptr, st));

@@ -171,28 +171,32 @@ __device__ __forceinline__ int64_t first_pass_len(const KParams& kp, int q) {
   return len;
 }
 
-// Four-phase first pass of one image: position i of the pass goes to the
-// tiles whose row and column are both even first, then (even row, odd
-// column), (odd row, even column) and (odd, odd), each group in raster
-// order.  No two tiles of a group touch, so tiles that run at the same time
-// are seldom neighbours (each would otherwise load the other's border before
-// it changes and ask for a re-visit), and every later group starts from
-// finished neighbours.
-__device__ __forceinline__ uint32_t phase_tile(uint32_t tx, uint32_t ty, uint32_t i) {
+// Four-phase first pass of one image: the tiles fall into four groups by
+// the parity of their row and column, group g holding rows of parity g >> 1
+// and columns of parity g & 1, and position i of the pass goes to the
+// groups one after the other, each in raster order.  No two tiles of a group
+// touch, so tiles that run at the same time are seldom neighbours (each
+// would otherwise load the other's border before it changes and ask for a
+// re-visit).  The groups go in the order 0, 1, 2, 3, or with `diag` in the
+// order 0, 3, 1, 2: the two diagonal groups first, so that every tile of the
+// last two groups, half the image, starts with all four edge neighbours
+// finished.
+__device__ __forceinline__ uint32_t phase_tile(uint32_t tx, uint32_t ty, uint32_t i, bool diag) {
   const uint32_t ex = (tx + 1) / 2, ox = tx / 2, ey = (ty + 1) / 2, oy = ty / 2;
+  auto size = [&](int g) { return ((g >> 1) ? oy : ey) * ((g & 1) ? ox : ex); };
+  const int g1 = diag ? 3 : 1, g2 = diag ? 1 : 2, g3 = diag ? 2 : 3;
   // the group sizes, compared one after the other (no indexed array: that
   // would live in scratch memory)
-  const uint32_t n0 = ey * ex, n1 = ey * ox, n2 = oy * ex;
   int p = 0;
-  if (i >= n0) {
-    i -= n0;
-    p = 1;
-    if (i >= n1) {
-      i -= n1;
-      p = 2;
-      if (i >= n2) {
-        i -= n2;
-        p = 3;
+  if (i >= size(0)) {
+    i -= size(0);
+    p = g1;
+    if (i >= size(g1)) {
+      i -= size(g1);
+      p = g2;
+      if (i >= size(g2)) {
+        i -= size(g2);
+        p = g3;
       }
     }
   }
@@ -206,13 +210,14 @@ __device__ __forceinline__ int64_t first_pass_tile(const KParams& kp, const DevI
   const uint32_t ii = (uint32_t)i, ch = (uint32_t)kp.chunk;
   const uint32_t c = (ii / ch) * (uint32_t)kp.nq + (uint32_t)q;
   const uint32_t t = c * ch + ii % ch;
-  if (kp.phase_tx > 0) return phase_tile((uint32_t)kp.phase_tx, (uint32_t)kp.phase_ty, t);
+  if (kp.phase_tx > 0)
+    return phase_tile((uint32_t)kp.phase_tx, (uint32_t)kp.phase_ty, t, kp.phase_diag != 0);
   if (kp.phase_tx < 0) {
     // a batch: the pass covers the images one after the other (tile ids),
     // each in its own four phases
     const DevImage& im = imgs[kp.tile_img[t]];
     return im.tile_base + phase_tile((uint32_t)im.tiles_x, (uint32_t)im.tiles_y,
-                                     t - (uint32_t)im.tile_base);
+                                     t - (uint32_t)im.tile_base, kp.phase_diag != 0);
   }
   if (kp.order_mul == 1 && kp.order_add == 0) return t;
   return (int64_t)(((uint64_t)t * kp.order_mul + kp.order_add) % (uint64_t)kp.ntiles);

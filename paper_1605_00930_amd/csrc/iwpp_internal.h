@@ -90,8 +90,10 @@ struct KParams {
   int32_t chunk;        // consecutive tile ids per queue chunk: tile t is in queue (t / chunk) % nq
   uint32_t order_mul, order_add;  // first-pass order: tile = (i * mul + add) mod ntiles
   // four-phase first pass (see phase_tile): the tile grid of a single image,
-  // or phase_tx = -1 for a batch, each image on its own (0: off)
+  // or phase_tx = -1 for a batch, each image on its own (0: off); phase_diag
+  // takes the two diagonal groups first
   int32_t phase_tx, phase_ty;
+  int32_t phase_diag;
   const int32_t* tile_img;  // batches: image index of every tile (or null)
   // packed side columns of I and J (column 0 and TW - 1 of every tile, row
   // after row), written by each tile from its first visit on (null: halo

@@ -179,6 +179,7 @@ extern "C" int iwpp_reconstruct_noalloc(const iwpp_image* img, int dtype, int co
     kp.phase_tx = one.tiles_x;
     kp.phase_ty = one.tiles_y;
   }
+  kp.phase_diag = rp.first_pass == 2;
   Carve c{};
   carve(r->base, ntiles, (int64_t)kp.nq * kp.qcap, rp.tile_h, esize, &c);
   const int64_t ncol = ntiles * 2 * rp.tile_h;

@@ -24,6 +24,7 @@ struct Resolved {
   uint32_t queue_waves;
   uint32_t flip;  // 0 dilation, ~0u erosion (from IWPP_FLAG_EROSION)
   int bands;      // mode 2: number of gray-level classes
+  int first_pass; // 1 first-visit groups by rows of the group grid, 2 diagonal groups first
 };
 
 // Device buffers of one launch context (a stream workspace, a batch plan or a

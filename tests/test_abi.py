@@ -75,6 +75,9 @@ def test_argument_errors_before_gpu_work(lib):
     p = iwpp.Params()
     p.mode = 3
     assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 0, ctypes.byref(p), None) == E
+    p = iwpp.Params()
+    p.first_pass = 3
+    assert lib.iwpp_reconstruct_async(ctypes.byref(im), 0, 8, 0, ctypes.byref(p), None) == E
     im32 = iwpp.Image(a + 1, b, 4, 4, 0)  # misaligned int32
     assert lib.iwpp_reconstruct_async(ctypes.byref(im32), 1, 8, 0, None, None) == E
     arr = (iwpp.Image * 1)(iwpp.Image(a, b, 0, 4, 0))

@@ -128,6 +128,7 @@ def test_row_pitch(iwpp):
     {"queue_waves": -1}, {"queue_waves": 2, "seed_queue": 100000, "sweeps": -1},
     {"mode": 2}, {"mode": 2, "bands": 3}, {"mode": 2, "bands": 300, "sweeps": 1},
     {"mode": 2, "bands": 64, "seed_queue": 100000, "queue_waves": 2},
+    {"first_pass": 1}, {"first_pass": 2}, {"first_pass": 2, "grid": 5},
 ])
 def test_parameters_do_not_change_the_result(iwpp, params):
     th = params.get("tile_h")
