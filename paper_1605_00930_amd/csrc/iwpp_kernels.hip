@@ -830,6 +830,34 @@ struct Tile {
   static constexpr int B = 16;
   static_assert(TH % (2 * B) == 0, "the vertical pass works two batches per iteration");
 
+  // step8x8 without the change bookkeeping, for rounds whose changes nobody
+  // reads (see solve): four instructions a step, and an s_nop in place of
+  // the bookkeeping keeps every DPP read of a chain value two wait states
+  // after its write.
+  __device__ static void step8x8n(int p, const int (&t)[8], const int (&ii)[8], int (&r)[8]) {
+    int b;
+#define IWPP_V8N(R, P, T, I)                                                    \
+  "v_max_i32 %8, " P ", " T "\n\t"                                             \
+  "s_nop 0\n\t"                                                                \
+  "v_max_i32_dpp %8, " P ", %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"      \
+  "v_max_i32_dpp %8, " P ", %8 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"      \
+  "v_min_i32 " R ", %8, " I "\n\t"
+    asm(IWPP_V8N("%0", "%9", "%10", "%18")
+        IWPP_V8N("%1", "%0", "%11", "%19")
+        IWPP_V8N("%2", "%1", "%12", "%20")
+        IWPP_V8N("%3", "%2", "%13", "%21")
+        IWPP_V8N("%4", "%3", "%14", "%22")
+        IWPP_V8N("%5", "%4", "%15", "%23")
+        IWPP_V8N("%6", "%5", "%16", "%24")
+        IWPP_V8N("%7", "%6", "%17", "%25")
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+          "=&v"(r[6]), "=&v"(r[7]), "=&v"(b)
+        : "v"(p), "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]), "v"(t[4]), "v"(t[5]), "v"(t[6]),
+          "v"(t[7]), "v"(ii[0]), "v"(ii[1]), "v"(ii[2]), "v"(ii[3]), "v"(ii[4]), "v"(ii[5]),
+          "v"(ii[6]), "v"(ii[7]));
+#undef IWPP_V8N
+  }
+
   // A batch of B steps of one 8-connected chain, eight steps per asm block.
   // jj holds the own J of each step on entry and the results on return;
   // `first` is the value step 0 takes with the chain in place of its own J
@@ -858,7 +886,26 @@ struct Tile {
     acc |= (uint32_t)(prev ^ jp);
   }
 
-  template <int D>
+  // steps8 without change bits (step8x8n).
+  __device__ static void steps8n(int& prev, int first, int (&jj)[B], const int (&ii)[B]) {
+#pragma unroll
+    for (int g = 0; g < B; g += 8) {
+      int t[8], i8[8], r[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        t[k] = jj[g + k];
+        i8[k] = ii[g + k];
+      }
+      if (g == 0) t[0] = first;
+      step8x8n(prev, t, i8, r);
+      prev = r[7];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) jj[g + k] = r[k];
+    }
+  }
+
+  // TRACK false: no change bits (d0 and d1 are left alone).
+  template <int D, bool TRACK = true>
   __device__ static void pass_vert(L& s, uint64_t& d0, uint64_t& d1) {
     const int x = lane();
     const int ys = D > 0 ? 0 : TH - 1;
@@ -875,7 +922,9 @@ struct Tile {
     };
     auto work = [&](int kb, int (&jj)[B], const int (&ii)[B]) {
       uint32_t acc = 0;
-      if constexpr (CONN == 8) {
+      if constexpr (CONN == 8 && !TRACK) {
+        steps8n(prev, imax(jj[0], corner), jj, ii);
+      } else if constexpr (CONN == 8) {
         steps8(prev, acc, imax(jj[0], corner), jj, ii);
       } else {
 #pragma unroll
@@ -884,14 +933,14 @@ struct Tile {
             prev = imin(max8(prev, k == 0 ? imax(jj[0], corner) : jj[k]), ii[k]);
           else
             prev = imin(imax(jj[k], prev), ii[k]);
-          acc |= (uint32_t)(prev ^ jj[k]);
+          if (TRACK) acc |= (uint32_t)(prev ^ jj[k]);
           jj[k] = prev;
         }
       }
       corner = LO;
 #pragma unroll
       for (int k = 0; k < B; ++k) s.J[G::at(ys + D * (kb + k), x)] = (T)jj[k];
-      if (__ballot(acc != 0u)) {
+      if (TRACK && __ballot(acc != 0u)) {
         // rows kb .. kb + B - 1 of the pass, i.e. this block of tile rows
         const int y0 = D > 0 ? kb : TH - kb - B;
         const uint64_t blk = ((1ull << B) - 1) << (y0 & 63);
@@ -998,7 +1047,7 @@ struct Tile {
   // is min(I, max of valid lower bounds of R), itself a valid lower bound of
   // R, which is all lane 31 needs from its lower neighbour; they write
   // nothing.
-  template <int D>
+  template <int D, bool TRACK = true>
   __device__ static void pass_horz(L& s, uint64_t& d0, uint64_t& d1) {
 #pragma unroll 1
     for (int g = 0; g < TH; g += 64) {
@@ -1034,7 +1083,9 @@ struct Tile {
           ii[k] = iv(s, yc, x);
           if (kFill) ff[k] = jv(s, fy, x);
         }
-        if constexpr (CONN == 8 && !kFill) {
+        if constexpr (CONN == 8 && !kFill && !TRACK) {
+          steps8n(prev, jj[0], jj, ii);
+        } else if constexpr (CONN == 8 && !kFill) {
           steps8(prev, acc, jj[0], jj, ii);
         } else {
 #pragma unroll
@@ -1045,7 +1096,7 @@ struct Tile {
             } else {
               prev = imin(imax(jj[k], prev), ii[k]);
             }
-            acc |= (uint32_t)(prev ^ jj[k]);
+            if (TRACK) acc |= (uint32_t)(prev ^ jj[k]);
             jj[k] = prev;
           }
         }
@@ -1055,11 +1106,13 @@ struct Tile {
         }
       }
       }
-      const uint64_t b = __ballot(live && acc != 0u);
-      if (g == 0)
-        d0 |= b;
-      else
-        d1 |= b;
+      if (TRACK) {
+        const uint64_t b = __ballot(live && acc != 0u);
+        if (g == 0)
+          d0 |= b;
+        else
+          d1 |= b;
+      }
       wsync();
     }
   }
@@ -1083,6 +1136,20 @@ struct Tile {
     return (d0 | d1) != 0;
   }
 
+  // One round of the four passes without change bits: every row counts as
+  // changed (the caller writes them all back) and the round as one that
+  // left work, so a scan of receivers follows.
+  __device__ static void untracked_round(L& s) {
+    uint64_t d0 = 0, d1 = 0;
+    pass_vert<+1, false>(s, d0, d1);
+    wsync();
+    pass_vert<-1, false>(s, d0, d1);
+    wsync();
+    pass_horz<+1, false>(s, d0, d1);
+    pass_horz<-1, false>(s, d0, d1);
+    for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 1;
+  }
+
   // Up to `budget` rounds of passes.  A pass that changes nothing leaves the
   // tile as it was, so four passes in a row that change nothing (one per
   // direction, in any cyclic order) all saw the same tile: it is then at a
@@ -1097,6 +1164,9 @@ struct Tile {
   //   state word (`watch`; null for none) is taken now: the halo is re-read
   //   and the rounds go on, instead of a re-run after this visit.
   static constexpr bool kStreaming = sizeof(T) == 1;
+  // int32 8-connected tiles of 32 rows: first visits run their round without
+  // change bits (see solve)
+  static constexpr bool kUntrackedFirst = sizeof(T) == 4 && CONN == 8 && TH == 32;
   enum { kRoundsLeft = 0, kFixed = 1, kEarly = 2 };
   __device__ static int sweep_rounds(L& s, int budget, int first_pass, VisitStats& vs,
                                      uint32_t* watch, const DevImage& im, int64_t y0, int64_t x0,
@@ -1402,11 +1472,22 @@ struct Tile {
     }
     // rounds of passes and scans read the whole tile
     if (seam) ensure_all_rows(s, im, y0, x0, kp);
+    // A first visit of an int32 tile (the initial solve: neither seeded nor
+    // resumed) with a budget of one round changes nearly every row, so its
+    // round skips the per-step change bits, writes every row back, and goes
+    // on to the scan as a round that left work would.
+    bool untracked = kUntrackedFirst && !seeded && !resume && !early && budget == 1;
     for (uint32_t guard = 0;; ++guard) {
-      const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, kp, t, tx, sides,
-                                 early);
-      if (r == kFixed) return false;
-      if (r == kEarly) return true;
+      if (untracked) {
+        untracked_round(s);
+        vs.rounds += 1;
+        untracked = false;
+      } else {
+        const int r = sweep_rounds(s, budget, first_pass, vs, watch, im, y0, x0, kp, t, tx,
+                                   sides, early);
+        if (r == kFixed) return false;
+        if (r == kEarly) return true;
+      }
       const int n = scan_receivers(s);
       if (n == 0) return false;
       if (!queue_loop(s, n, vs, waves, iter_limit, hit_limit, false, im, y0, x0, kp))
