@@ -50,6 +50,27 @@ __device__ __forceinline__ void st_coherent(__attribute__((address_space(1))) T*
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sixteen bytes per lane through a buffer resource over `bytes` bytes from
+// `base`: ld_coherent_b128 with the cache policy an agent-scope relaxed load
+// gets on gfx950 (sc1), for marker rows; ld_plain_b128 without it, for the
+// mask, which nothing writes during a launch.  One instruction then carries
+// four rows of a 64-column int32 tile where dword loads carry one.
+typedef int int4v __attribute__((ext_vector_type(4)));
+constexpr int kPolicySc1 = 16;  // cache-policy bit of a buffer access: sc1
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const void* base, uint32_t bytes) {
+  // word 3: 32-bit data format (a raw buffer access needs a non-zero one)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ int4v ld_coherent_b128(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kPolicySc1);
+}
+__device__ __forceinline__ int4v ld_plain_b128(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                               uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+
 // Wait until every memory access this wavefront has issued is complete (an
 // agent-scope store is then visible to the whole device), and keep the
 // compiler from moving memory accesses across the wait.  Used after the
@@ -640,7 +661,10 @@ __device__ __forceinline__ TilePos tile_pos(const DevImage& one, const DevImage*
 // Along its share of the first pass a worker keeps three tiles in flight:
 // the tile t it solves; the next tile n, whose loads it issues into
 // registers once t is solved and its activation mask taken, before t is
-// written back, so that their round trip overlaps the write-back; and the
+// written back, so that their round trip overlaps the write-back (for int32
+// tiles the loads and stores together stay within the 63 memory operations
+// a wavefront can have outstanding; a tile at the image edge is loaded at
+// its visit instead, see Tile::prefetchable); and the
 // tile after n, whose state word goes pending -> running (its flags read in
 // the same round trip) right after t's solve.  t is published only after
 // n's solve: by then its stores have completed, and the drain before the
@@ -702,19 +726,31 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
   // and its visit follows.  The registers of the next tile are written on
   // every path into the write-back (zeros when there is none), so the
   // compiler never keeps them live across a solve.
+  // A first-pass tile the inner loop could not prefetch (see
+  // Tile::prefetchable) comes back here as `carry` with its flags; the tile
+  // after it is already taken (nx).
+  int carry = -1, carry_fv = 0;
   for (;;) {
     uint32_t c0 = (uint32_t)now();
     bool first_pass = false;
     int fv = 0;
-    int t = next_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, first_pass, fv);
-    if (t < 0) break;
+    int t;
+    const bool carried = carry >= 0;
+    if (carried) {
+      t = carry;
+      fv = carry_fv;
+      carry = -1;
+    } else {
+      t = next_tile(ctl, queue, kp, state, visited, imgs, q, grid, qs, first_pass, fv);
+      if (t < 0) break;
+    }
     TilePos tp = tile_pos<TH>(one, imgs, kp, t);
     // a re-visit stages its seams (load_seam); anything else is issued into
     // the registers and committed at once
     bool seam = false;
     if constexpr (TP::kSeamVisits) seam = !(fv & 1) && kp.colJ;
     if (!seam) TP::issue(P, tp.im, tp.y0, tp.x0, kp, t, tp.tx, fv >> 1);
-    take_next();  // the tile after t
+    if (!carried) take_next();  // the tile after t
     // the tile written back before this one, awaiting its publication
     // (dt < 0: none): its neighbour requests (lanes 0..8) and whether it was
     // a first visit
@@ -761,12 +797,15 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
       int amax = 0;
       const uint32_t act = TP::activation_mask(s, tp.y0, tp.x0, false, amax);
       TilePos np = tp;
+      bool nissued = false;
       if (nt >= 0) {
         np = tile_pos<TH>(one, imgs, kp, nt);
-        TP::issue(P, np.im, np.y0, np.x0, kp, nt, np.tx, nfv >> 1);
-      } else {
-        TP::clear_pre(P);
+        nissued = TP::prefetchable(np.im, np.y0, np.x0);
       }
+      if (nissued)
+        TP::issue_prefetch(P, np.im, np.y0, np.x0, kp, nt, np.tx, nfv >> 1);
+      else
+        TP::clear_pre(P);
       TP::store(s, tp.im, tp.y0, tp.x0, kp, t, first);
       const int n = neighbour_request(tp.im, tp.ty, tp.tx, act);
       c0 = (uint32_t)now();
@@ -776,15 +815,19 @@ __device__ __forceinline__ void prefetch_worker(DevImage one, const DevImage* __
         if (viol) atomicOr((int*)&ctl->status.v, ST_MARKER_GT_MASK);
         if (hit) abort_launch(ctl, queue, kp, grid, ST_INTERNAL);
       }
-      if (nt < 0) {
-        // no next tile: publish this one now (its write-back and packed
-        // side columns complete first)
+      if (!nissued) {
+        // no next tile, or one the outer loop loads: publish this one now
+        // (its write-back and packed side columns complete first)
         drain_memory();
         if (lead && first) st_coherent(&visited[t], (uint8_t)1);
         publish_requests(ctl, queue, kp, state, t, n, 0, ws, qs.credit, true, true);
         uint32_t c5 = (uint32_t)now();
         ws.t_sync += c5 - c0;
         c0 = c5;
+        if (nt >= 0) {
+          carry = nt;
+          carry_fv = nfv;
+        }
         break;
       }
       dt = t;

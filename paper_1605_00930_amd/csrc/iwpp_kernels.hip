@@ -105,6 +105,41 @@ struct Lds {
 // whose pixel rose during the propagation phase.
 constexpr uint16_t kRose = 0x8000u;
 
+// Issued halo rows of a tile, one int per row and lane (Q false), or four
+// consecutive rows to a quad (Q true), so that a 16-byte load of four
+// columns fills a quad in place (see Tile::issue_t).
+template <int ROWS, bool Q>
+struct PreRows {
+  int j[ROWS], i[ROWS];
+  __device__ __forceinline__ int gj(int k) const { return j[k]; }
+  __device__ __forceinline__ int gi(int k) const { return i[k]; }
+  __device__ __forceinline__ void set(int k, int a, int b) {
+    j[k] = a;
+    i[k] = b;
+  }
+};
+template <int ROWS>
+struct PreRows<ROWS, true> {
+  static constexpr int NQ = ROWS / 4;  // rows past the quads: one int each
+  int4v jq[NQ], iq[NQ];
+  int jt[ROWS - 4 * NQ], it[ROWS - 4 * NQ];
+  __device__ __forceinline__ int gj(int k) const {
+    return k < 4 * NQ ? jq[k >> 2][k & 3] : jt[k - 4 * NQ];
+  }
+  __device__ __forceinline__ int gi(int k) const {
+    return k < 4 * NQ ? iq[k >> 2][k & 3] : it[k - 4 * NQ];
+  }
+  __device__ __forceinline__ void set(int k, int a, int b) {
+    if (k < 4 * NQ) {
+      jq[k >> 2][k & 3] = a;
+      iq[k >> 2][k & 3] = b;
+    } else {
+      jt[k - 4 * NQ] = a;
+      it[k - 4 * NQ] = b;
+    }
+  }
+};
+
 template <typename T, int CONN, int TH>
 struct Tile {
   using G = Geo<T, TH>;
@@ -314,32 +349,90 @@ struct Tile {
   static constexpr bool kPrefetch = sizeof(T) == 4 && TH == 32;
   static constexpr int kSideEntries = 2 * TH + 4;
   static constexpr int kSideRegs = (kSideEntries + 63) / 64;
+  // int32 tiles of 32 rows load halo rows 0 .. 31 sixteen bytes to a lane:
+  // eight instructions per array instead of 32, so that the next tile's
+  // loads and the current tile's stores stay under the 63 memory operations
+  // a wavefront can have outstanding (past that the issue waits a whole
+  // round trip).
+  static constexpr bool kWideRows = sizeof(T) == 4 && TH == 32;
+  // Issued values of a tile: halo row k of J and I for this lane's column
+  // (r.gj(k), r.gi(k)), except that int32 tiles of 32 rows (kWideRows) hold
+  // rows 0 .. 31 four columns to a lane (quad q: columns 4 (l % 16) .. + 3
+  // of row 4 q + l / 16).
   struct Pre {
-    int j[G::ROWS], i[G::ROWS];
+    PreRows<G::ROWS, kWideRows> r;
     int ej[kSideRegs], ei[kSideRegs];
   };
+  __device__ __forceinline__ static bool wide_rows_ok(const DevImage& im) {
+    return kWideRows && (((uintptr_t)im.J | (uintptr_t)im.I) % 16) == 0 && im.ld % 4 == 0 &&
+           im.ld <= (1 << 24);
+  }
 
-  template <bool INNER>
+  // FAST: the caller has checked prefetchable() (inner tile, and for int32
+  // rows that allow 16-byte loads), so only that load path is compiled.
+  template <bool INNER, bool FAST = false>
   __device__ __forceinline__ static void issue_t(Pre& p, const DevImage& im, int64_t y0,
                                                  int64_t x0, const KParams& kp, int64_t t,
                                                  int64_t tx, int sides) {
     const gptr<const T> gJ = (gptr<const T>)im.J;
     const gptr<const T> gI = (gptr<const T>)im.I;
     const int lo_raw = in((T)LO, kp.flip);
-    const int64_t gx = x0 + lane();
+    // the lane index through an empty asm: values derived from it are then
+    // computed here, not kept in registers for the whole launch
+    int ln = lane();
+    asm volatile("" : "+v"(ln));
+    const int64_t gx = x0 + ln;
     const bool c_in = gx < im.W;
+    int k0 = 0;
+    if constexpr (kWideRows) {
+      // halo rows 0 .. 31 (image rows y0 - 1 .. y0 + 30), four columns to a
+      // lane: quad q holds columns 4 (l % 16) .. + 3 of row 4 q + l / 16
+      static_assert(G::ROWS == 34, "two rows follow the 32 of the quads");
+      const int rr = ln >> 4, cq = 4 * (ln & 15);
+      if (FAST || (INNER && wide_rows_ok(im))) {
+        // sixteen bytes to a lane, one instruction per quad
+        const uint32_t row_b = (uint32_t)im.ld * 4u;
+        const int64_t o = (y0 - 1) * im.ld + x0;
+        const __amdgpu_buffer_rsrc_t rj = rows_rsrc((const void*)(gJ + o), 32u * row_b);
+        const __amdgpu_buffer_rsrc_t ri = rows_rsrc((const void*)(gI + o), 32u * row_b);
+        const uint32_t voff = (uint32_t)rr * row_b + 4u * (uint32_t)cq;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          p.r.jq[q] = ld_coherent_b128(rj, voff, 4u * (uint32_t)q * row_b);
+          p.r.iq[q] = ld_plain_b128(ri, voff, 4u * (uint32_t)q * row_b);
+        }
+      } else if constexpr (!FAST) {
+        // edge tiles and unaligned images: the same layout, a pixel at a time
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int64_t gy = y0 - 1 + 4 * q + rr;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t gxe = x0 + cq + e;
+            int a = lo_raw, b = lo_raw;
+            if (INNER || (gy >= 0 && gy < im.H && gxe < im.W)) {
+              a = (int)ld_coherent(&gJ[gy * im.ld + gxe]);
+              b = (int)gI[gy * im.ld + gxe];
+            }
+            p.r.jq[q][e] = a;
+            p.r.iq[q][e] = b;
+          }
+        }
+      }
+      k0 = 32;
+    }
 #pragma unroll
     for (int k = 0; k < G::ROWS; ++k) {
+      if (k < k0) continue;
       const int64_t gy = y0 - 1 + k;
-      p.j[k] = p.i[k] = lo_raw;
-      if (INNER || (gy >= 0 && gy < im.H && c_in)) {
-        p.j[k] = (int)ld_coherent(&gJ[gy * im.ld + gx]);
-        p.i[k] = (int)gI[gy * im.ld + gx];
-      }
+      if (INNER || (gy >= 0 && gy < im.H && c_in))
+        p.r.set(k, (int)ld_coherent(&gJ[gy * im.ld + gx]), (int)gI[gy * im.ld + gx]);
+      else
+        p.r.set(k, lo_raw, lo_raw);
     }
 #pragma unroll
     for (int k = 0; k < kSideRegs; ++k) {
-      const int e = lane() + 64 * k;
+      const int e = ln + 64 * k;
       p.ej[k] = p.ei[k] = lo_raw;
       if (e < kSideEntries) side_load<INNER>(im, y0, x0, kp, t, tx, sides, e, p.ej[k], p.ei[k]);
     }
@@ -353,9 +446,26 @@ struct Tile {
     else
       issue_t<false>(p, im, y0, x0, kp, t, tx, sides);
   }
+  // The persistent worker's next-tile prefetch takes only tiles with a
+  // single load path: inside the image with their halo and, for int32, rows
+  // that allow 16-byte loads.  With several paths the compiler's wait counts
+  // follow each of them into the block after, and the first register write
+  // of the fast path then waits for every memory operation in flight (the
+  // previous publication's atomics among them).  Other tiles load at their
+  // visit (load()).
+  __device__ __forceinline__ static bool prefetchable(const DevImage& im, int64_t y0,
+                                                      int64_t x0) {
+    const bool inner = y0 >= 1 && y0 + TH < im.H && x0 >= 1 && x0 + TW < im.W;
+    return inner && (!kWideRows || wide_rows_ok(im));
+  }
+  __device__ __forceinline__ static void issue_prefetch(Pre& p, const DevImage& im, int64_t y0,
+                                                        int64_t x0, const KParams& kp, int64_t t,
+                                                        int64_t tx, int sides) {
+    issue_t<true, true>(p, im, y0, x0, kp, t, tx, sides);
+  }
   __device__ __forceinline__ static void clear_pre(Pre& p) {
 #pragma unroll
-    for (int k = 0; k < G::ROWS; ++k) p.j[k] = p.i[k] = 0;
+    for (int k = 0; k < G::ROWS; ++k) p.r.set(k, 0, 0);
 #pragma unroll
     for (int k = 0; k < kSideRegs; ++k) p.ej[k] = p.ei[k] = 0;
   }
@@ -368,10 +478,39 @@ struct Tile {
     for (int y = lane(); y < TH; y += 64) s.rowdirty[y] = 0;
     wsync();
     bool viol = false;
+    int y_lane = 0;  // halo rows before this one are already staged
+    if constexpr (kWideRows) {
+      {
+        // rows 0 .. 31, four columns to a lane (issue_t)
+        const int rr = lane() >> 4, c = 4 * (lane() & 15) + 1;
+        uint32_t clamped = 0;  // bit q: this lane clamped a pixel of quad q
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int yy = 4 * q + rr;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int a = in((T)p.r.jq[q][e], flip);
+            const int b = in((T)p.r.iq[q][e], flip);
+            clamped |= (uint32_t)(a > b) << q;
+            s.J[yy * G::P + c + e] = (T)imin(a, b);
+            s.I[yy * G::P + c + e] = (T)b;
+          }
+        }
+        // a clamped pixel's row goes back to memory; inside the tile (halo
+        // row 0 is the row above it) it means J > I on a first visit
+        clamped &= rr == 0 ? ~1u : ~0u;
+        for (uint32_t m = clamped; m; m &= m - 1) {
+          s.rowdirty[4 * __builtin_ctz(m) + rr - 1] = 1;
+          viol = viol || first;
+        }
+        y_lane = 32;
+      }
+    }
 #pragma unroll
     for (int yy = 0; yy < G::ROWS; ++yy) {
-      int a = in((T)p.j[yy], flip);
-      const int b = in((T)p.i[yy], flip);
+      if (yy < y_lane) continue;
+      int a = in((T)p.r.gj(yy), flip);
+      const int b = in((T)p.r.gi(yy), flip);
       if (a > b) {
         if (yy >= 1 && yy <= TH) {
           viol = viol || first;

@@ -17,9 +17,10 @@ relaxed atomic, served coherently device-wide (`sc1` on gfx950), and only the
 mask I, which nothing writes, is read with plain loads.  Two checks hold the
 sources to that: a lint of the device sources (every subscript of a pointer
 into the marker or the packed columns sits inside `ld_coherent` /
-`st_coherent`; three planted plain accesses must be caught), and the compiled
-persistent kernels (every global store carries `sc1`, and no `buffer_wbl2` or
-`buffer_inv` appears).
+`st_coherent`, and a buffer resource built over the marker is read only with
+`ld_coherent_b128`, the 16-byte load with the same cache policy; four planted
+plain accesses must be caught), and the compiled persistent kernels (every
+global store carries `sc1`, and no `buffer_wbl2` or `buffer_inv` appears).
 """
 from __future__ import annotations
 
@@ -173,6 +174,16 @@ def lint_coherent_access(sources):
                     found.append("%s:%d: %s" % (fname, i, line.strip()))
             if names and re.search(r"\b(?:%s)\s*->" % "|".join(map(re.escape, names)), line):
                 found.append("%s:%d: %s" % (fname, i, line.strip()))
+        # buffer resources over the marker: every use is a coherent 16-byte load
+        shared = re.compile("|".join([_SHARED_BASES] + [r"\b%s\b" % re.escape(n) for n in names]))
+        for m in re.finditer(r"(\w+)\s*=\s*rows_rsrc\(([^;]*)\);", code):
+            if not shared.search(m.group(2)):
+                continue
+            for u in re.finditer(r"\b%s\b" % re.escape(m.group(1)), code[m.end():]):
+                at = m.end() + u.start()
+                if not re.search(r"\bld_coherent_b128\s*\(\s*$", code[:at]):
+                    i = code.count("\n", 0, at) + 1
+                    found.append("%s:%d: %s" % (fname, i, lines[i - 1].strip()))
     return sorted(set(found))
 
 
@@ -187,6 +198,8 @@ def test_marker_and_side_columns_are_accessed_coherently():
     assert {"gJ", "row"} <= _shared_pointer_names(code)
     assert "gI" not in _shared_pointer_names(code)  # the mask is read-only
     assert "gS" in _shared_pointer_names(_strip_comments(src["iwpp_edt.hip"]))
+    # the int32 tiles' 16-byte marker loads go through a buffer resource
+    assert re.search(r"\brj\s*=\s*rows_rsrc\(\(const void\*\)\(gJ\b", code)
     assert lint_coherent_access(src) == []
 
 
@@ -194,6 +207,7 @@ def test_marker_and_side_columns_are_accessed_coherently():
     ("(int)ld_coherent(&gJ[gy * im.ld + gx])", "(int)gJ[gy * im.ld + gx]"),
     ("st_coherent(row, w[q]);", "*row = w[q];"),
     ("ld_coherent(&((gptr<const T>)kp.colI)[k])", "((gptr<const T>)kp.colI)[k]"),
+    ("p.r.jq[q] = ld_coherent_b128(rj,", "p.r.jq[q] = ld_plain_b128(rj,"),
 ])
 def test_lint_catches_a_plain_access(old, new):
     src = _read_sources()
