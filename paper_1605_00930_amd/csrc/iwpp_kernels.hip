@@ -1376,7 +1376,7 @@ struct Tile {
     int fa = jv(s, -1, fx), fb = jv(s, 0, fx);
     constexpr int R = 8;
     static_assert(TH % 32 == 0, "receiver rows are gathered 32 at a time");
-    uint32_t bits = 0;  // bit y % 32: pixel (y, x) is a receiver
+    uint32_t bits = 0;  // bit y % 32: pixel (y, x) is a receiver (see below)
 #pragma unroll 1
     for (int yb = 0; yb < TH; yb += R) {
       int jn[R], fn[R], ii[R];
@@ -1395,15 +1395,23 @@ struct Tile {
         } else {
           m = max_sides(imax(imax(ja, jn[k]), fb), jb);
         }
-        bits |= (uint32_t)(jb < ii[k] && m > jb) << ((yb & 31) + k);
+        // a receiver iff min(m, I) > J; the bit goes in at the bottom and
+        // the earlier rows move up (bits = 2 bits + carry, two instructions)
+        const int mi = imin(m, ii[k]);
+        asm("v_cmp_gt_i32 vcc, %1, %2\n\t"
+            "v_addc_co_u32 %0, vcc, %0, %0, vcc"
+            : "+v"(bits)
+            : "v"(mi), "v"(jb)
+            : "vcc");
         ja = jb;
         jb = jn[k];
         fa = fb;
         fb = fn[k];
       }
       // after each 32 rows: compact the rows that hold a receiver, in row
-      // order (most rows hold none)
+      // order (most rows hold none); bit 31 - y holds row y until reversed
       if (((yb + R) & 31) == 0) {
+        bits = __builtin_bitreverse32(bits);
         const int g = (yb + R - 32) * TW + x;
         for (uint32_t rows = wave_or(bits); rows; rows &= rows - 1) {
           const int y = __builtin_ctz(rows);
