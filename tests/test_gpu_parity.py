@@ -28,17 +28,20 @@ def iwpp():
     return lib
 
 
-def run(iwpp, I, J, conn=8, ld_pad=0, check=True, **kw):
+def run(iwpp, I, J, conn=8, ld_pad=0, check=True, col0=0, **kw):
+    """Reconstruct on the device; with ld_pad the images sit in wider
+    buffers (row pitch W + ld_pad) starting at column col0 of each row."""
     import torch
 
     dev = torch.device("cuda:0")
     H, W = I.shape
     if ld_pad:
+        assert 0 <= col0 <= ld_pad
         bigJ = torch.zeros((H, W + ld_pad), dtype=torch.from_numpy(J).dtype, device=dev)
         bigI = torch.zeros_like(bigJ)
-        bigJ[:, :W] = torch.from_numpy(J).to(dev)
-        bigI[:, :W] = torch.from_numpy(I).to(dev)
-        Jt, It = bigJ[:, :W], bigI[:, :W]
+        bigJ[:, col0:col0 + W] = torch.from_numpy(J).to(dev)
+        bigI[:, col0:col0 + W] = torch.from_numpy(I).to(dev)
+        Jt, It = bigJ[:, col0:col0 + W], bigI[:, col0:col0 + W]
     else:
         Jt = torch.from_numpy(np.ascontiguousarray(J)).to(dev)
         It = torch.from_numpy(np.ascontiguousarray(I)).to(dev)
@@ -115,6 +118,21 @@ def test_row_pitch(iwpp):
     announce("pitch 300x250 ld=250+37")
     got, _ = run(iwpp, I, J, 8, ld_pad=37)
     same(got, expect(I, J, 8), "pitched")
+
+
+@pytest.mark.parametrize("ld_pad,col0", [(4, 0), (4, 1), (8, 3), (37, 0)])
+@pytest.mark.parametrize("conn", [8, 4])
+def test_int32_row_alignment(iwpp, ld_pad, col0, conn):
+    """int32 tiles inside the image load their rows sixteen bytes to a lane
+    when every row starts 16-byte aligned (pitch a multiple of four pixels,
+    aligned base); other images take the pixel-at-a-time path for every
+    tile.  Both, against the oracle: a pitch of W + 4 with the image at
+    column 0 (sixteen-byte loads, pitch != width) and at column 1 (rows
+    4-byte aligned only), W + 8 at column 3, W + 37."""
+    I, J = synth.c3_i32(H=330, W=452)
+    announce("int32 pitch 330x452 ld=452+%d col0=%d conn %d" % (ld_pad, col0, conn))
+    got, _ = run(iwpp, I, J, conn, ld_pad=ld_pad, col0=col0)
+    same(got, expect(I, J, conn), "int32 ld=W+%d col0=%d" % (ld_pad, col0))
 
 
 # ------------------------------------------------------------------ parameters
