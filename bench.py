@@ -356,7 +356,7 @@ def bench_single(args, torch, iwpp, workload=None, steps=None, warmup=None, quie
         tuned = {k: v for k, v in iwpp.autotune(Jt0, It, 8, stream=stream).items() if v}
         log("autotuned in %.1f s: %s" % (time.perf_counter() - t0, tuned))
         params.update(tuned)
-    for k in ("tile_h", "sweeps", "mode", "seed_queue", "queue_waves", "bands"):
+    for k in ("tile_h", "sweeps", "mode", "seed_queue", "queue_waves", "bands", "first_pass"):
         v = getattr(args, k)
         if v is not None:
             params[k] = v
@@ -467,6 +467,8 @@ def bench_batched(args, torch, iwpp):
         params["tile_h"] = args.tile_h
     if args.sweeps is not None:
         params["sweeps"] = args.sweeps
+    if args.first_pass is not None:
+        params["first_pass"] = args.first_pass
     plan = iwpp.Batch(list(zip(work, masks)), 8, params=params)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -669,6 +671,8 @@ def main():
     ap.add_argument("--mode", type=int, default=None)
     ap.add_argument("--seed-queue", dest="seed_queue", type=int, default=None)
     ap.add_argument("--queue-waves", dest="queue_waves", type=int, default=None)
+    ap.add_argument("--first-pass", dest="first_pass", type=int, default=None, choices=[1, 2],
+                    help="order of the first visits' tile groups: 1 by rows, 2 diagonals first")
     ap.add_argument("--bands", type=int, default=None, help="gray-level classes (mode 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
