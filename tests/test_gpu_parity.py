@@ -302,6 +302,29 @@ def test_batched_uneven_sizes(iwpp):
         same(pairs[k][0].cpu().numpy(), expect(I, J, 8), "batched image %d" % k)
 
 
+@pytest.mark.parametrize("first_pass", [1, 2])
+def test_batched_first_pass_orders(iwpp, first_pass):
+    """Each image of a batch runs its own four groups of first visits; both
+    group orders, uint8 and int32 images of uneven sizes, against the
+    oracle."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(41 + first_pass)
+    batch = synth.c4(n=6, lo=40, hi=500)
+    pairs = [(torch.from_numpy(J).to(dev), torch.from_numpy(I).to(dev)) for I, J in batch]
+    announce("batched u8, first_pass %d" % first_pass)
+    iwpp.reconstruct_batched(pairs, 8, params={"first_pass": first_pass})
+    for k, (I, J) in enumerate(batch):
+        same(pairs[k][0].cpu().numpy(), expect(I, J, 8), "u8 image %d" % k)
+    b32 = [synth.c3_i32(H=int(h), W=int(w)) for h, w in rng.integers(33, 400, size=(5, 2))]
+    p32 = [(torch.from_numpy(J).to(dev), torch.from_numpy(I).to(dev)) for I, J in b32]
+    announce("batched int32, first_pass %d" % first_pass)
+    iwpp.reconstruct_batched(p32, 8, params={"first_pass": first_pass})
+    for k, (I, J) in enumerate(b32):
+        same(p32[k][0].cpu().numpy(), expect(I, J, 8), "int32 image %d" % k)
+
+
 def test_batch_plan_graph_replays(iwpp):
     import torch
 
